@@ -1,0 +1,219 @@
+"""Benchmark of the NLINV hot path on one MI355X.
+
+Workload: the real-time series of 160 px frames (320 x 320 grid), 10 virtual
+coils (PCA from 30), 15 spokes x 320 samples per frame in 5 rotated turns,
+7 Newton x 20 CG steps, temporal regularisation to the previous frame.
+A step is one frame per series: gridding (z = F^H y, plus the PSF kernel the
+first time a turn is seen) and the IRGNM reconstruction.
+
+  plain   : one series, frames solved one after another (batch 1)  -> `value`
+  batched : 16 independent series advanced together (batch 16)    -> `batched`
+
+Inputs are seeded synthetic data generated on the host before timing and
+copied to the GPU; the timed region starts with everything resident in HBM.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N, J, J_PHYS, K, U, M, C = 160, 10, 30, 15, 5, 7, 20
+HBM_PEAK_GBS = 8000.0
+
+
+def _series(args):
+    seed, frames, threads = args
+    from threadpoolctl import threadpool_limits
+    from paper_1701_08361_amd import synth
+    with threadpool_limits(threads):
+        s = synth.real_time_series(seed=seed, N=N, J=J, J_phys=J_PHYS, K=K, U=U, frames=frames)
+    return s.traj, s.y, s.turn
+
+
+def make_data(seeds, frames, workers):
+    if workers > 1 and len(seeds) > 1:
+        ctx = mp.get_context("fork")
+        with ctx.Pool(min(workers, len(seeds))) as pool:
+            return pool.map(_series, [(s, frames, 1) for s in seeds])
+    return [_series((s, frames, None)) for s in seeds]
+
+
+def kernel_bytes(kind: str, B: int, fast: bool, turns_distinct: int) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel class (each input read
+    once, each output written once)."""
+    G, R, Gc = 2 * N, N, N // 2
+    s2 = 8 if fast else 16
+    if kind == "toeplitz_rows":      # U2 rows in + out, PSF kernel rows
+        return B * J * G * R * 2 * s2 + turns_distinct * G * G * 4
+    if kind == "coil_cols":          # U1 in, coil images + image + p in, U2 out
+        return B * J * (Gc * R * 16 + R * R * 8 + G * R * s2) + B * R * R * (8 + 16 + 16)
+    if kind == "back_cols":          # U2 in, coils in, PR out, U1 out
+        return B * J * (G * R * s2 + R * R * 8 + R * R * 8 + Gc * R * 16) + B * R * R * (8 + 16)
+    raise ValueError(kind)
+
+
+def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel):
+    """Advance B series by warmup + steps frames; returns per-step ms, total ms,
+    and the timer reading for `timer_kernel` over the timed steps."""
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=(1 if fast else 0))
+    import numpy as np
+    traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()  # [F,B,K,S_r,2]
+    y = torch.from_numpy(np.stack([d[1] for d in data], axis=1)).cuda()     # [F,B,J,S]
+    turn = data[0][2]
+    F = traj.shape[0]
+    z = torch.empty(B, J, N, N, dtype=torch.complex64, device="cuda")
+    xa = torch.empty(B, plan.X, dtype=torch.complex64, device="cuda")
+    xb = torch.empty_like(xa)
+    img = torch.empty(B, N, N, dtype=torch.float32, device="cuda")
+    # every PSF kernel is computed once up front (part of plan set-up, not of a frame)
+    for t in range(U):
+        plan.psf(traj[t, 0].contiguous(), t)
+    torch.cuda.synchronize()
+
+    def frame(n, xprev, xout):
+        f = n % F
+        tn = [int(turn[f])] * B
+        plan.grid(traj[f], y[f], z=z)
+        plan.reconstruct(z, tn, xprev=xprev, xhat=xout, init=(1 if xprev is None else 2), img=img)
+
+    xprev = None
+    bufs = [xa, xb]
+    for n in range(warmup):
+        frame(n, xprev, bufs[n & 1])
+        xprev = bufs[n & 1]
+    torch.cuda.synchronize()
+    if timer_kernel:
+        plan.timer_enable(timer_kernel)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        n = warmup + i
+        ev[i][0].record()
+        frame(n, xprev, bufs[n & 1])
+        ev[i][1].record()
+        xprev = bufs[n & 1]
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    per = [a.elapsed_time(b) for a, b in ev]
+    kt = plan.timer_read() if timer_kernel else (0.0, 0)
+    plan.close()
+    return per, total_ms, kt
+
+
+def pct(v, q):
+    v = sorted(v)
+    k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[k]
+
+
+def cpu_baseline(seconds_hint: float = 30.0):
+    """The FP64 oracle (as it stands) on frame 0 of the series: gridding + PSF
+    kernel + 7 x 20 IRGNM.  One frame is the bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import nlinv_oracle as O
+    from paper_1701_08361_amd import synth
+    s = synth.real_time_series(seed=2, N=N, J=J, J_phys=J_PHYS, K=K, U=U, frames=1)
+    g = O.Geometry.make(N, J)
+    t0 = time.perf_counter()
+    z = O.grid(s.y[0], s.traj[0], g.R)
+    P = O.psf_kernel(s.traj[0], g.R, g.G)
+    x = O.reconstruct(g, z, P, newton=M, cg_iters=C)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(x).all()
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 frame (frame 0 of the 160px 10ch series: exact gridding, PSF kernel, "
+                      f"7x20 IRGNM) in {dt:.1f} s on {os.cpu_count()} host CPUs "
+                      f"({platform.processor() or platform.machine()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed frames per series (plain)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch-steps", type=int, default=40)
+    ap.add_argument("--mode", choices=["both", "plain", "batched"], default="both")
+    ap.add_argument("--fast", action="store_true", help="float32 half-transformed grid (NLINV_F_FAST)")
+    ap.add_argument("--kernel", default="toeplitz_rows", help="kernel class timed for the roofline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    frames_plain = min(100, args.warmup + args.steps)
+    frames_batch = args.warmup + args.batch_steps
+    t_gen = time.perf_counter()
+    plain_data = make_data([2], frames_plain, 1) if args.mode != "batched" else None
+    batch_data = (make_data(list(range(2, 2 + args.batch)), frames_batch, args.workers)
+                  if args.mode != "plain" else None)
+    t_gen = time.perf_counter() - t_gen
+
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    import torch
+    from paper_1701_08361_amd import nlinv as nl
+    if not os.path.exists(nl.LIB_PATH):
+        from paper_1701_08361_amd import build
+        build.build(verbose=False)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nl.load()
+
+    kbytes, kms, klaunch = 0.0, 0.0, 0
+    out = {"metric": "frames/sec + p99 frame latency, 160px 10ch NLINV, batched vs plain, 1 GPU",
+           "unit": "frames/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    if plain_data is not None:
+        per, total, (tms, tl) = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, args.fast, args.kernel)
+        fps = args.steps / (total / 1e3)
+        out.update({"value": fps, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps,
+                    "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}})
+        kbytes += tl * kernel_bytes(args.kernel, 1, args.fast, 1)
+        kms += tms
+        klaunch += tl
+    if batch_data is not None:
+        B = args.batch
+        per, total, (tms, tl) = run_mode(torch, nl, batch_data, B, args.batch_steps, args.warmup, args.fast,
+                                         args.kernel)
+        out["batched"] = {"batch": B, "steps": args.batch_steps, "fps": B * args.batch_steps / (total / 1e3),
+                          "ms_per_step": total / args.batch_steps,
+                          "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}}
+        kbytes += tl * kernel_bytes(args.kernel, B, args.fast, 1)
+        kms += tms
+        klaunch += tl
+        if plain_data is None:
+            out.update({"value": out["batched"]["fps"], "steps": args.batch_steps, "warmup": args.warmup,
+                        "ms_per_step": out["batched"]["ms_per_step"]})
+    out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
+                                 "5 turns, 7 Newton x 20 CG, temporal regularisation",
+                     "plain_batch": 1, "batched_batch": args.batch, "fast_grid": bool(args.fast),
+                     "data_gen_s": round(t_gen, 1)}
+    if klaunch:
+        achieved = kbytes / (kms / 1e3) / 1e9
+        out["roofline"] = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": kms / klaunch * 1e3, "launches": klaunch}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

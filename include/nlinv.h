@@ -1,0 +1,190 @@
+/*
+ * nlinv.h -- C-ABI of the MI355X (gfx950) NLINV hot path.
+ *
+ * NLINV (Sec. 2.2 of Schaetz, Voit, Frahm, Uecker, "Accelerated Computing in
+ * MRI: Real-Time Imaging Using Non-Linear Inverse Reconstruction") jointly
+ * estimates an image rho and J coil sensitivities c_j from multi-channel
+ * radial k-space data y by minimising ||F x - y||^2 + alpha ||W (x - x_prev)||^2
+ * (the objective of Sec. 2.2) with the iteratively regularised Gauss-Newton
+ * method (the IRGNM update equation of Sec. 2.2), each Newton system being
+ * solved by conjugate gradients on DF^H DF + alpha I (the normal-operator
+ * equation of Sec. 2.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Sizes: G = grid side (2N unless given), R = G/2 reconstructed side
+ *    (= N), G_c = G/4 coil-spectrum side (Sec. 3.2, coil cropping),
+ *    S = K * S_r samples per channel, X = R*R + J*G_c*G_c unknowns.
+ *    Supported grids: G = 2N in {64, 128, 256, 320, 384, 448}.
+ *  - complex64 is interleaved (re, im) float32 (nlinv_c64).
+ *  - Images are R x R row-major [y][x]; pixel (0,0) sits at (x, y) =
+ *    (-R/2, -R/2) pixels.  The unknown x_hat = W x is stored as the image rho
+ *    [R][R] followed by J coil spectra c_hat_j [G_c][G_c] (row-major
+ *    [kappa_y][kappa_x], DC at (G_c/2, G_c/2)); c_j = W^-1 c_hat_j.
+ *  - Trajectories are float32 [K][S_r][2] (kx, ky) in cycles/pixel; radial
+ *    data are [J][K*S_r].  The non-uniform Fourier transform is
+ *    (F u)_s = (1/R) sum_r u(r) exp(-i 2 pi k_s . r), unitary when the samples
+ *    are the R x R Cartesian frequencies of the field of view.
+ *  - The batch dimension B (plan parameter `batch`) is outermost in every
+ *    array: B independent problems of the same shape are processed per call.
+ *  - All d_* pointers are device pointers owned by the caller; they must be
+ *    8-byte aligned.  h_* pointers are host pointers read before the call
+ *    returns.  Inputs and outputs must not overlap unless stated.
+ *  - The plan owns only host metadata.  All device scratch memory (tables,
+ *    PSF kernels, intermediate buffers, CG vectors, FP64 partial sums) lives
+ *    in the caller-supplied workspace; no call allocates device memory.
+ *  - Every call enqueues asynchronously on the plan's HIP stream and returns;
+ *    nothing synchronises except nlinv_sync.  A plan is used by one host
+ *    thread at a time; calls on one plan are ordered by its stream.
+ *  - Errors: 0 = NLINV_OK, negative codes below.  Arguments are validated on
+ *    the host before anything is enqueued, so a failing call has no side
+ *    effects.  Launch failures are reported as NLINV_E_HIP; asynchronous
+ *    device errors surface at the next call or at nlinv_sync.
+ *    nlinv_last_error returns a description that stays valid until the next
+ *    call on the same plan.
+ */
+#ifndef NLINV_H
+#define NLINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nlinv_plan_s* nlinv_plan;
+typedef struct { float re, im; } nlinv_c64;
+
+enum {
+  NLINV_OK = 0,
+  NLINV_E_ARG = -1,        /* NULL / misaligned pointer, bad value          */
+  NLINV_E_SIZE = -2,       /* unsupported size combination                 */
+  NLINV_E_WORKSPACE = -3,  /* workspace missing or too small               */
+  NLINV_E_HIP = -4,        /* HIP runtime / launch error                   */
+  NLINV_E_STATE = -5,      /* call order violated (e.g. PSF not computed)  */
+};
+
+/* Plan flags.
+ * NLINV_F_FAST: store the half-transformed grid of the PSF convolution (the
+ *   largest intermediate, [J][G][R] per item) in float32 instead of float64.
+ *   Halves that buffer's HBM traffic; CG amplifies the extra rounding, so
+ *   reconstructions drift further from the float64 reference (the default
+ *   keeps every operator intermediate except the coil images and the
+ *   per-channel products in float64). */
+enum { NLINV_F_FAST = 1 };
+
+/* Plan parameters.  nlinv_params_default fills the defaults noted here. */
+typedef struct {
+  int32_t N;          /* image side (required)                                  */
+  int32_t G;          /* grid side; 0 -> 2N (Sec. 3.2, G = 2 gamma N, gamma = 1)  */
+  int32_t J;          /* channels (virtual coils), 1..64                         */
+  int32_t K;          /* spokes per frame, odd                                   */
+  int32_t S_r;        /* samples per spoke; 0 -> 2N                              */
+  int32_t U;          /* turns = number of cached PSF kernels, 1..64 (default 1) */
+  int32_t batch;      /* B >= 1, <= 64 (default 1)                               */
+  int32_t newton;     /* M Newton steps (default 7)                              */
+  int32_t cg;         /* C CG iterations per Newton step (default 10)            */
+  int32_t flags;      /* NLINV_F_* bits (default 0)                              */
+  double alpha0;      /* first regularisation weight (default 1.0)               */
+  double alpha_q;     /* alpha_{n+1} = max(alpha_n * alpha_q, alpha_min) (0.5)   */
+  double alpha_min;   /* (default 0.0)                                           */
+  double sob_a;       /* Sobolev weight (1 + a |k|^2)^l, Fig. weight_func: 880   */
+  double sob_l;       /*                                                    : 16 */
+} nlinv_params;
+
+/* Fill `p` with the defaults above (N, K left 0).  Never fails for non-NULL p. */
+int nlinv_params_default(nlinv_params* p);
+
+/* Validate `p` and return the workspace size in bytes.  Host-only: needs no GPU. */
+int nlinv_workspace_size(const nlinv_params* p, size_t* bytes);
+
+/* Derived sizes of a parameter set (host-only).  Any output may be NULL. */
+int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc,
+                int64_t* S, int64_t* X);
+
+/* Create a plan on the current HIP device.  `stream` is a hipStream_t (NULL =
+ * default stream).  `d_workspace` (>= nlinv_workspace_size bytes, 256-byte
+ * aligned) is owned by the caller and must stay allocated until
+ * nlinv_plan_destroy.  Uploads the FP64-computed tables (twiddles, Sobolev
+ * weights) and waits for that upload before returning. */
+int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace,
+                      size_t ws_bytes, nlinv_plan* out);
+int nlinv_plan_destroy(nlinv_plan plan);
+int nlinv_set_stream(nlinv_plan plan, void* stream);
+
+/* PSF kernel of one turn (Sec. 2.2 footnote; Fig. flow: convolution with the
+ * point-spread function on the twofold oversampled grid).
+ * psf(d) = (1/R^2) sum_s exp(+i 2 pi k_s . d) over lags |d_x|,|d_y| <= R-1 (exact sum),
+ * P = unnormalised 2D DFT of psf on the G-grid; P is real and is cached in the
+ * workspace under `turn` (0 <= turn < U).  d_traj: [K][S_r][2]. */
+int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn);
+
+/* Gridding (Sec. 3.1, preprocessing): z_j = F^H y_j on the R x R field of view,
+ * z_j(r) = (1/R) sum_s y_{j,s} exp(+i 2 pi k_s . r), exact sum.
+ * d_traj [B][K][S_r][2], d_y [B][J][S] -> d_z [B][J][R][R].
+ * If h_turn != NULL (host [B]), the PSF kernel of every turn h_turn[b] not yet
+ * cached is computed from d_traj[b] (as nlinv_psf). */
+int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y,
+               const int32_t* h_turn, nlinv_c64* d_z);
+
+/* NLINV reconstruction (Sec. 2.2: IRGNM, M Newton steps, each solved with C CG
+ * iterations on DF^H DF + alpha_n I applied through the PSF convolution).
+ *   d_z     [B][J][R][R]  gridded data (nlinv_grid)
+ *   h_turn  host [B]      PSF kernel per item (must have been computed)
+ *   d_xprev [B][X]        regularisation target x_hat_prev; NULL -> (rho = 1, c = 0)
+ *   d_xhat  [B][X]        in: initial guess (init = 0); out: result
+ *   init    0: use d_xhat as given; 1: start from (rho = 1, c = 0);
+ *           2: start from d_xprev (copied; d_xprev must not be NULL)
+ *   d_img   [B][R][R] float32, |rho| sqrt(sum_j |c_j|^2), or NULL
+ *   d_coils [B][J][R][R] coil images c_j = W^-1 c_hat_j of the result, or NULL
+ * d_xhat must not overlap d_xprev or d_z. */
+int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_turn,
+                      const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init,
+                      float* d_img, nlinv_c64* d_coils);
+
+/* Operators at the linearisation point d_xhat [B][X] (Sec. 2.2), mapping
+ * between the unknowns and the radial measurement space [B][J][S]:
+ *   F_hat(x)_j    = F(rho . W^-1 c_hat_j)
+ *   DF(dx)_j      = F(c_j d_rho + rho W^-1 d_c_hat_j)
+ *   DF^H(dy)      = (sum_j conj(c_j) F^H dy_j ; W^-H (conj(rho) F^H dy_j))
+ * F is the exact non-uniform DFT (no gridding approximation), so DF and DF^H
+ * are adjoint up to float32 rounding. */
+int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat,
+                  nlinv_c64* d_y);
+int nlinv_apply_DF(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat,
+                   const nlinv_c64* d_dx, nlinv_c64* d_dy);
+int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat,
+                    const nlinv_c64* d_dy, nlinv_c64* d_dx);
+
+/* The CG operator (normal-operator equation and t_j of Sec. 2.2):
+ * d_q = DF^H DF d_p + alpha d_p, with F^H F applied as the PSF convolution of
+ * turn h_turn[b].  d_xhat, d_p, d_q: [B][X]. */
+int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
+                       double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
+
+/* Coil images c_j = W^-1 c_hat_j [B][J][R][R] and/or the combined image
+ * |rho| sqrt(sum_j |c_j|^2) [B][R][R] of d_xhat; either output may be NULL. */
+int nlinv_coils(nlinv_plan plan, const nlinv_c64* d_xhat, nlinv_c64* d_coils, float* d_img);
+
+/* Block until all work enqueued on the plan's stream has finished. */
+int nlinv_sync(nlinv_plan plan);
+
+/* Description of the last error on `plan` (or of the last plan-less error
+ * when plan == NULL).  Never NULL. */
+const char* nlinv_last_error(nlinv_plan plan);
+
+/* Kernel timing for roofline measurement: while enabled, HIP events bracket
+ * every launch of kernel class `kernel_id` (NLINV_KT_*) on the plan stream.
+ * nlinv_timer_read waits for the stream, returns the summed duration (ms) and
+ * launch count since the last read, and resets them. */
+enum { NLINV_KT_NONE = 0, NLINV_KT_TOEPLITZ_ROWS = 1, NLINV_KT_COIL_COLS = 2,
+       NLINV_KT_BACK_COLS = 3, NLINV_KT_CG_UPDATE = 4, NLINV_KT_COIL_ROWS = 5,
+       NLINV_KT_COILH_ROWS = 6, NLINV_KT_GRID = 7 };
+int nlinv_timer_enable(nlinv_plan plan, int32_t kernel_id);
+int nlinv_timer_read(nlinv_plan plan, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLINV_H */

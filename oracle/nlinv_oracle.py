@@ -23,7 +23,11 @@ Readings of points the paper leaves open (all shared with the HIP path):
     [-floor(n/2), ceil(n/2)-1]; the PSF kernel P is the unnormalised DFT of
     the PSF so that F_u^-1 (P . F_u v) is the cyclic convolution psf * v.
   - Image pixels sit at integer coordinates r in [-R/2, R/2)^2, R = G/2;
-    the non-uniform DFT uses exp(-i 2 pi k.r) with k in cycles/pixel.
+    the non-uniform DFT uses exp(-i 2 pi k.r) with k in cycles/pixel and
+    the unitary scale 1/R (the same normalisation as F_u: F is unitary when
+    the samples are the R x R Cartesian frequencies of the field of view).
+    Without it the data term of every Newton system is R^2 times heavier
+    than alpha_n and CG becomes too ill-conditioned for float32.
   - The PSF is kept on lags |d_x|,|d_y| <= R-1 (the only lags a difference
     of two FOV pixels can take); all other lags of the G-grid are zero,
     which makes P real.
@@ -143,18 +147,19 @@ def _phase_factors(traj: np.ndarray, R: int, sign: int):
 
 
 def nudft(u: np.ndarray, traj: np.ndarray) -> np.ndarray:
-    """(F u)_s = sum_r u(r) exp(-i 2 pi k_s.r): images [..., R, R] -> [..., S].
+    """(F u)_s = (1/R) sum_r u(r) exp(-i 2 pi k_s.r): images [..., R, R] -> [..., S].
     Evaluated exactly; the sum over r is split into its x and y parts."""
     R = u.shape[-1]
     ex, ey = _phase_factors(traj, R, -1)
     a = u @ ex.T                                   # [..., y, s] = sum_x u[y,x] ex[s,x]
-    return np.einsum("sy,...ys->...s", ey, a)
+    return np.einsum("sy,...ys->...s", ey, a) / R
 
 
 def nudft_adjoint(v: np.ndarray, traj: np.ndarray, R: int) -> np.ndarray:
-    """(F^H v)(r) = sum_s v_s exp(+i 2 pi k_s.r): [..., S] -> [..., R, R]."""
+    """(F^H v)(r) = (1/R) sum_s v_s exp(+i 2 pi k_s.r): [..., S] -> [..., R, R]."""
     ex, ey = _phase_factors(traj, R, +1)
-    return np.einsum("sy,...s,sx->...yx", ey, v, ex, optimize=True)
+    v = np.asarray(v, dtype=np.complex128)
+    return np.matmul(ey.T * v[..., None, :], ex) / R   # [..., y, s] @ [s, x]
 
 
 def nudft_matrix(traj: np.ndarray, R: int) -> np.ndarray:
@@ -162,7 +167,7 @@ def nudft_matrix(traj: np.ndarray, R: int) -> np.ndarray:
     k = np.asarray(traj, dtype=np.float64).reshape(-1, 2)
     c = centred(R).astype(np.float64)
     Y, X = np.meshgrid(c, c, indexing="ij")
-    return np.exp(-2j * np.pi * (np.outer(k[:, 0], X.ravel()) + np.outer(k[:, 1], Y.ravel())))
+    return np.exp(-2j * np.pi * (np.outer(k[:, 0], X.ravel()) + np.outer(k[:, 1], Y.ravel()))) / R
 
 
 # ---------------------------------------------------------------------------
@@ -175,12 +180,13 @@ def grid(y: np.ndarray, traj: np.ndarray, R: int) -> np.ndarray:
 
 
 def psf_lags(traj: np.ndarray, R: int) -> np.ndarray:
-    """psf(d) = sum_s exp(+i 2 pi k_s.d) for lags d in [-(R-1), R-1]^2 -> [2R-1, 2R-1] [dy, dx]."""
+    """psf(d) = (1/R^2) sum_s exp(+i 2 pi k_s.d) for lags d in [-(R-1), R-1]^2
+    -> [2R-1, 2R-1] [dy, dx], so that (F^H F u)(r) = sum_r' psf(r - r') u(r')."""
     k = np.asarray(traj, dtype=np.float64).reshape(-1, 2)
     d = np.arange(-(R - 1), R).astype(np.float64)
     ex = np.exp(2j * np.pi * np.outer(k[:, 0], d))
     ey = np.exp(2j * np.pi * np.outer(k[:, 1], d))
-    return ey.T @ ex
+    return (ey.T @ ex) / (R * R)
 
 
 def psf_kernel(traj: np.ndarray, R: int, G: int, keep_imag: bool = False) -> np.ndarray:

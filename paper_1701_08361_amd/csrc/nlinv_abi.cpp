@@ -1,0 +1,583 @@
+// C-ABI of the NLINV hot path: argument validation, workspace layout, FP64
+// host tables and the launch sequences of each entry point.
+#include "nlinv.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nlinv_internal.h"
+
+using nlv::Bufs;
+using nlv::Partials;
+using nlv::Shape;
+
+struct nlinv_plan_s {
+  nlinv_params p;
+  Shape s;
+  Bufs w;
+  const nlv::GTable* t = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<char> psf_valid;
+  std::string err;
+  int timer_kid = NLINV_KT_NONE;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  size_t ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;   // errors not tied to a plan
+
+int fail(nlinv_plan plan, int code, const std::string& msg) {
+  if (plan) plan->err = msg; else g_err = msg;
+  return code;
+}
+
+int fail_hip(nlinv_plan plan, hipError_t e, const char* what) {
+  std::string m = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return fail(plan, NLINV_E_HIP, m);
+}
+
+#define NLV_HIP(plan, expr)                                  \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return fail_hip(plan, e_, #expr);  \
+  } while (0)
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bool supported_grid(int G) {
+  return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 448;
+}
+
+// Validates the parameters, fills the shape and the workspace layout.
+struct Layout {
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, total;
+};
+
+int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
+  auto bad = [&](int code, const char* m) { *err = m; return code; };
+  if (!p) return bad(NLINV_E_ARG, "params is NULL");
+  if (p->N <= 0) return bad(NLINV_E_ARG, "N must be positive");
+  const int G = p->G == 0 ? 2 * p->N : p->G;
+  if (G != 2 * p->N) return bad(NLINV_E_SIZE, "only G = 2N is supported");
+  if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384 or 448");
+  if (p->J < 1 || p->J > 64) return bad(NLINV_E_ARG, "J must be in [1, 64]");
+  if (p->K < 1 || (p->K % 2) == 0) return bad(NLINV_E_ARG, "K must be a positive odd number");
+  const int S_r = p->S_r == 0 ? 2 * p->N : p->S_r;
+  if (S_r < 1) return bad(NLINV_E_ARG, "S_r must be positive");
+  if ((long long)p->K * S_r > (1 << 24)) return bad(NLINV_E_SIZE, "K * S_r too large");
+  if (p->U < 1 || p->U > 64) return bad(NLINV_E_ARG, "U must be in [1, 64]");
+  if (p->batch < 1 || p->batch > nlv::MAXB) return bad(NLINV_E_ARG, "batch must be in [1, 64]");
+  if (p->newton < 0 || p->newton > 1000) return bad(NLINV_E_ARG, "newton must be in [0, 1000]");
+  if (p->cg < 1 || p->cg > 100000) return bad(NLINV_E_ARG, "cg must be in [1, 100000]");
+  if (p->flags & ~NLINV_F_FAST) return bad(NLINV_E_ARG, "unknown flag bits");
+  if (!(p->alpha0 > 0.0) || !std::isfinite(p->alpha0)) return bad(NLINV_E_ARG, "alpha0 must be positive and finite");
+  if (!(p->alpha_q > 0.0 && p->alpha_q <= 1.0)) return bad(NLINV_E_ARG, "alpha_q must be in (0, 1]");
+  if (!(p->alpha_min >= 0.0) || !std::isfinite(p->alpha_min)) return bad(NLINV_E_ARG, "alpha_min must be >= 0");
+  if (!(p->sob_a >= 0.0) || !(p->sob_l >= 0.0) || !std::isfinite(p->sob_a) || !std::isfinite(p->sob_l))
+    return bad(NLINV_E_ARG, "Sobolev parameters must be finite and >= 0");
+
+  Shape& S = *s;
+  S.B = p->batch;
+  S.J = p->J;
+  S.G = G;
+  S.R = G / 2;
+  S.GC = G / 4;
+  S.S = p->K * S_r;
+  S.U = p->U;
+  S.X = (long long)S.R * S.R + (long long)S.J * S.GC * S.GC;
+  S.NT = S.R / nlv::TW;
+  S.NX3 = S.J * S.GC / nlv::ROWS;
+  S.NY2 = S.J * S.NT;
+  S.NCI = (S.R * S.R + nlv::CHUNK - 1) / nlv::CHUNK;
+  S.NCH = (int)((S.X + nlv::CHUNK - 1) / nlv::CHUNK);
+  int st = S.NY2 + S.NX3;
+  if (S.NX3 + S.NCI > st) st = S.NX3 + S.NCI;
+  if (S.NCH > st) st = S.NCH;
+  S.stride = st;
+  S.fast = (p->flags & NLINV_F_FAST) != 0;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t B = S.B, J = S.J, Gs = S.G, R = S.R, GC = S.GC, X = (size_t)S.X;
+  const size_t c8 = 8;    // complex64
+  const size_t c16 = 16;  // complex128
+  L->tw = take(Gs * c16);
+  L->dinv = take(GC * GC * 4);
+  L->P = take((size_t)S.U * Gs * Gs * 4);
+  L->psf = take(Gs * Gs * c16);
+  L->CO = take(B * J * R * R * c8);
+  L->U1 = take(B * J * GC * R * c16);
+  L->U2 = take(B * J * Gs * R * (S.fast ? c8 : c16));
+  L->PR = take(B * J * R * R * c8);
+  L->IMG = take(B * J * R * R * c8);
+  L->H = take(B * X * c16);
+  L->Rv = take(B * X * c16);
+  L->Pv0 = take(B * X * c16);
+  L->Pv1 = take(B * X * c16);
+  L->Q = take(B * X * c16);
+  L->pq = take(B * (size_t)S.stride * 8);
+  L->rr0 = take(B * (size_t)S.stride * 8);
+  L->rr1 = take(B * (size_t)S.stride * 8);
+  L->total = off;
+  return NLINV_OK;
+}
+
+int check_ptr(nlinv_plan plan, const void* ptr, const char* name, bool allow_null = false) {
+  if (!ptr) {
+    if (allow_null) return NLINV_OK;
+    return fail(plan, NLINV_E_ARG, std::string(name) + " is NULL");
+  }
+  if (!aligned8(ptr)) return fail(plan, NLINV_E_ARG, std::string(name) + " is not 8-byte aligned");
+  return NLINV_OK;
+}
+
+#define NLV_CHECK(expr)         \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != NLINV_OK) return rc_; \
+  } while (0)
+
+int check_plan(nlinv_plan plan) {
+  if (!plan) return fail(nullptr, NLINV_E_ARG, "plan is NULL");
+  plan->err.clear();
+  return NLINV_OK;
+}
+
+// Event-bracketed launch of kernel class `kid` when the timer is enabled for it.
+template <class F>
+hipError_t timed(nlinv_plan plan, int kid, F&& f) {
+  if (plan->timer_kid != kid || kid == NLINV_KT_NONE) return f();
+  if (plan->ev_used + 2 > plan->ev.size()) {
+    for (int i = 0; i < 256; ++i) {
+      hipEvent_t e;
+      hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) return he;
+      plan->ev.push_back(e);
+    }
+  }
+  hipEvent_t a = plan->ev[plan->ev_used], b = plan->ev[plan->ev_used + 1];
+  hipError_t he = hipEventRecord(a, plan->stream);
+  if (he != hipSuccess) return he;
+  he = f();
+  if (he != hipSuccess) return he;
+  he = hipEventRecord(b, plan->stream);
+  if (he != hipSuccess) return he;
+  plan->ev_used += 2;
+  return hipSuccess;
+}
+
+int turns_of(nlinv_plan plan, const int32_t* h_turn, nlv::TurnArgs* t) {
+  if (!h_turn) return fail(plan, NLINV_E_ARG, "h_turn is NULL");
+  std::memset(t, 0, sizeof(*t));
+  for (int b = 0; b < plan->s.B; ++b) {
+    const int v = h_turn[b];
+    if (v < 0 || v >= plan->s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
+    if (!plan->psf_valid[v])
+      return fail(plan, NLINV_E_STATE, "PSF kernel of turn " + std::to_string(v) + " not computed (nlinv_grid / nlinv_psf)");
+    t->t[b] = v;
+  }
+  return NLINV_OK;
+}
+
+// c_j = W^-1 c_hat_j of `xh` into `co`.
+int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
+  const Shape& s = plan->s;
+  const Partials none{};
+  NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, plan->w, plan->stream, xh); }));
+  NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+            return plan->t->cols_fwd(s, plan->w, plan->stream, 0, co, xh, nullptr, nullptr, nullptr,
+                                        none, nullptr);
+          }));
+  return NLINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nlinv_params_default(nlinv_params* p) {
+  if (!p) return fail(nullptr, NLINV_E_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->U = 1;
+  p->batch = 1;
+  p->newton = 7;
+  p->cg = 10;
+  p->alpha0 = 1.0;
+  p->alpha_q = 0.5;
+  p->alpha_min = 0.0;
+  p->sob_a = 880.0;
+  p->sob_l = 16.0;
+  return NLINV_OK;
+}
+
+int nlinv_workspace_size(const nlinv_params* p, size_t* bytes) {
+  if (!bytes) return fail(nullptr, NLINV_E_ARG, "bytes is NULL");
+  Shape s;
+  Layout L;
+  std::string err;
+  const int rc = derive(p, &s, &L, &err);
+  if (rc != NLINV_OK) return fail(nullptr, rc, err);
+  *bytes = L.total;
+  return NLINV_OK;
+}
+
+int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc, int64_t* S, int64_t* X) {
+  Shape s;
+  Layout L;
+  std::string err;
+  const int rc = derive(p, &s, &L, &err);
+  if (rc != NLINV_OK) return fail(nullptr, rc, err);
+  if (R) *R = s.R;
+  if (G) *G = s.G;
+  if (Gc) *Gc = s.GC;
+  if (S) *S = s.S;
+  if (X) *X = s.X;
+  return NLINV_OK;
+}
+
+int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
+                      nlinv_plan* out) {
+  if (!out) return fail(nullptr, NLINV_E_ARG, "out is NULL");
+  *out = nullptr;
+  Shape s;
+  Layout L;
+  std::string err;
+  int rc = derive(p, &s, &L, &err);
+  if (rc != NLINV_OK) return fail(nullptr, rc, err);
+  if (!d_workspace) return fail(nullptr, NLINV_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) & 255u)
+    return fail(nullptr, NLINV_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(nullptr, NLINV_E_WORKSPACE,
+                "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  nlinv_plan plan = new (std::nothrow) nlinv_plan_s;
+  if (!plan) return fail(nullptr, NLINV_E_ARG, "out of host memory");
+  plan->p = *p;
+  plan->s = s;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  plan->psf_valid.assign(s.U, 0);
+  plan->t = nlv::table_for(s.G);
+  if (!plan->t) {
+    delete plan;
+    return fail(nullptr, NLINV_E_SIZE, "no kernels for this grid size");
+  }
+  char* base = static_cast<char*>(d_workspace);
+  Bufs& w = plan->w;
+  w.tw = reinterpret_cast<double2*>(base + L.tw);
+  w.dinv = reinterpret_cast<float*>(base + L.dinv);
+  w.P = reinterpret_cast<float*>(base + L.P);
+  w.psf = reinterpret_cast<double2*>(base + L.psf);
+  w.CO = reinterpret_cast<float2*>(base + L.CO);
+  w.U1 = reinterpret_cast<double2*>(base + L.U1);
+  w.U2 = static_cast<void*>(base + L.U2);
+  w.PR = reinterpret_cast<float2*>(base + L.PR);
+  w.IMG = reinterpret_cast<float2*>(base + L.IMG);
+  w.H = reinterpret_cast<double2*>(base + L.H);
+  w.Rv = reinterpret_cast<double2*>(base + L.Rv);
+  w.Pv[0] = reinterpret_cast<double2*>(base + L.Pv0);
+  w.Pv[1] = reinterpret_cast<double2*>(base + L.Pv1);
+  w.Q = reinterpret_cast<double2*>(base + L.Q);
+  w.pq = reinterpret_cast<double*>(base + L.pq);
+  w.rr[0] = reinterpret_cast<double*>(base + L.rr0);
+  w.rr[1] = reinterpret_cast<double*>(base + L.rr1);
+
+  // FP64 host tables, stored as float32.
+  std::vector<double2> tw(s.G);
+  for (int m = 0; m < s.G; ++m) {
+    const double a = 2.0 * M_PI * m / s.G;
+    tw[m] = make_double2(std::cos(a), std::sin(a));
+  }
+  std::vector<float> dinv((size_t)s.GC * s.GC);
+  for (int i = 0; i < s.GC; ++i) {
+    for (int ic = 0; ic < s.GC; ++ic) {
+      const double ky = (double)(i - s.GC / 2) / s.G, kx = (double)(ic - s.GC / 2) / s.G;
+      const double wgt = std::pow(1.0 + p->sob_a * (kx * kx + ky * ky), p->sob_l);
+      dinv[(size_t)i * s.GC + ic] = (float)(1.0 / (s.G * wgt));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(w.tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, plan->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(w.dinv, dinv.data(), dinv.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) {
+    std::string m = std::string("HIP error uploading tables: ") + hipGetErrorString(e);
+    delete plan;
+    return fail(nullptr, NLINV_E_HIP, m);
+  }
+  *out = plan;
+  return NLINV_OK;
+}
+
+int nlinv_plan_destroy(nlinv_plan plan) {
+  if (!plan) return fail(nullptr, NLINV_E_ARG, "plan is NULL");
+  for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+  delete plan;
+  return NLINV_OK;
+}
+
+int nlinv_set_stream(nlinv_plan plan, void* stream) {
+  NLV_CHECK(check_plan(plan));
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  return NLINV_OK;
+}
+
+int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  if (turn < 0 || turn >= plan->s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
+  NLV_HIP(plan, nlv::launch_psf(plan->s, plan->w, plan->stream, d_traj, turn));
+  plan->psf_valid[turn] = 1;
+  return NLINV_OK;
+}
+
+int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const int32_t* h_turn,
+               nlinv_c64* d_z) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  NLV_CHECK(check_ptr(plan, d_y, "d_y"));
+  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
+  const Shape& s = plan->s;
+  if (h_turn) {
+    for (int b = 0; b < s.B; ++b)
+      if (h_turn[b] < 0 || h_turn[b] >= s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
+    for (int b = 0; b < s.B; ++b) {
+      const int t = h_turn[b];
+      if (plan->psf_valid[t]) continue;
+      NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj + (size_t)b * s.S * 2, t));
+      plan->psf_valid[t] = 1;
+    }
+  }
+  NLV_HIP(plan, timed(plan, NLINV_KT_GRID, [&] {
+            return nlv::launch_grid(s, plan->stream, d_traj, reinterpret_cast<const float2*>(d_y),
+                                    reinterpret_cast<float2*>(d_z));
+          }));
+  return NLINV_OK;
+}
+
+int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_turn,
+                      const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init, float* d_img,
+                      nlinv_c64* d_coils) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_xprev, "d_xprev", true));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img", true));
+  NLV_CHECK(check_ptr(plan, d_coils, "d_coils", true));
+  if (init < 0 || init > 2) return fail(plan, NLINV_E_ARG, "init must be 0, 1 or 2");
+  if (init == 2 && !d_xprev) return fail(plan, NLINV_E_ARG, "init = 2 needs d_xprev");
+  if (d_xprev && (const void*)d_xprev == (const void*)d_xhat)
+    return fail(plan, NLINV_E_ARG, "d_xhat must not alias d_xprev");
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  hipStream_t st = plan->stream;
+  float2* xh = reinterpret_cast<float2*>(d_xhat);
+  const float2* xp = reinterpret_cast<const float2*>(d_xprev);
+  const float2* z = reinterpret_cast<const float2*>(d_z);
+  const Partials none{};
+
+  if (init == 1) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, nullptr, 1));
+  if (init == 2) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, xp, 2));
+
+  double alpha = plan->p.alpha0;
+  for (int n = 0; n < plan->p.newton; ++n) {
+    // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
+    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, w, st, xh); }));
+    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+              return plan->t->cols_fwd(s, w, st, 0, w.CO, xh, nullptr, nullptr, nullptr, none, w.U2);
+            }));
+    NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
+    NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
+              return plan->t->cols_back(s, w, st, 1, w.U2, w.CO, xh, z, nullptr, 0.0);
+            }));
+    NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+              return plan->t->coilh_rows(s, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
+            }));
+    NLV_HIP(plan, nlv::launch_cg_init(s, w, st, xh, xp, alpha));
+
+    int ncur = s.NX3 + s.NCI, nprev = 0;
+    const int C = plan->p.cg;
+    for (int i = 0; i < C; ++i) {
+      double2* pc = w.Pv[i & 1];
+      double2* pp = w.Pv[(i + 1) & 1];
+      const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
+      const bool upd = i > 0;
+      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
+                return plan->t->coil_rows_cg(s, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
+                                                upd ? pc : nullptr, sc);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+                return plan->t->cols_fwd(s, w, st, 1, w.CO, xh, upd ? pp : pc, upd ? w.Rv : nullptr,
+                                            upd ? pc : nullptr, sc, w.U2);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
+                return plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr, pc, alpha);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+                return plan->t->coilh_rows(s, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
+                return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh, alpha);
+              }));
+      nprev = ncur;
+      ncur = s.NCH;
+    }
+    alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
+  }
+
+  if (d_img || d_coils) {
+    float2* co = d_coils ? reinterpret_cast<float2*>(d_coils) : w.CO;
+    NLV_CHECK(coils_into(plan, xh, co));
+    if (d_img) NLV_HIP(plan, nlv::launch_image(s, st, xh, co, d_img));
+  }
+  return NLINV_OK;
+}
+
+int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat, nlinv_c64* d_y) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_y, "d_y"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  const Partials none{};
+  NLV_HIP(plan, plan->t->coil_rows(s, w, plan->stream, xh));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 2, w.CO, xh, nullptr, nullptr, nullptr, none, w.IMG));
+  NLV_HIP(plan, nlv::launch_nudft_fwd(s, plan->stream, d_traj, w.IMG, reinterpret_cast<float2*>(d_y)));
+  return NLINV_OK;
+}
+
+int nlinv_apply_DF(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat, const nlinv_c64* d_dx,
+                   nlinv_c64* d_dy) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_dx, "d_dx"));
+  NLV_CHECK(check_ptr(plan, d_dy, "d_dy"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  const float2* dx = reinterpret_cast<const float2*>(d_dx);
+  const Partials none{};
+  NLV_CHECK(coils_into(plan, xh, w.CO));
+  NLV_HIP(plan, nlv::launch_to_double(s, plan->stream, w.Pv[0], dx));
+  NLV_HIP(plan, plan->t->coil_rows_cg(s, w, plan->stream, w.Pv[0], nullptr, nullptr, none));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 3, w.CO, xh, w.Pv[0], nullptr, nullptr, none, w.IMG));
+  NLV_HIP(plan, nlv::launch_nudft_fwd(s, plan->stream, d_traj, w.IMG, reinterpret_cast<float2*>(d_dy)));
+  return NLINV_OK;
+}
+
+int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat, const nlinv_c64* d_dy,
+                    nlinv_c64* d_dx) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_dy, "d_dy"));
+  NLV_CHECK(check_ptr(plan, d_dx, "d_dx"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  float2* dx = reinterpret_cast<float2*>(d_dx);
+  NLV_CHECK(coils_into(plan, xh, w.CO));
+  NLV_HIP(plan, nlv::launch_grid(s, plan->stream, d_traj, reinterpret_cast<const float2*>(d_dy), w.IMG));
+  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, w.IMG, w.CO, xh, nullptr, nullptr, 0.0));
+  NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, xh, nullptr, 0.0, w.Q, nullptr));
+  NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, dx));
+  return NLINV_OK;
+}
+
+int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat, double alpha,
+                       const nlinv_c64* d_p, nlinv_c64* d_q) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_p, "d_p"));
+  NLV_CHECK(check_ptr(plan, d_q, "d_q"));
+  if (!std::isfinite(alpha)) return fail(plan, NLINV_E_ARG, "alpha must be finite");
+  if ((const void*)d_p == (const void*)d_q) return fail(plan, NLINV_E_ARG, "d_q must not alias d_p");
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  hipStream_t st = plan->stream;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  const float2* p = reinterpret_cast<const float2*>(d_p);
+  float2* q = reinterpret_cast<float2*>(d_q);
+  const Partials none{};
+  NLV_CHECK(coils_into(plan, xh, w.CO));
+  double2* pd = w.Pv[0];
+  NLV_HIP(plan, nlv::launch_to_double(s, st, pd, p));
+  NLV_HIP(plan, plan->t->coil_rows_cg(s, w, st, pd, nullptr, nullptr, none));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pd, nullptr, nullptr, none, w.U2));
+  NLV_HIP(plan, plan->t->toep_rows(s, w, st, turns));
+  NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr, pd, alpha));
+  NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, pd, xh, nullptr, alpha, w.Q, nullptr));
+  NLV_HIP(plan, nlv::launch_finalize(s, w, st, pd, alpha, q));
+  return NLINV_OK;
+}
+
+int nlinv_coils(nlinv_plan plan, const nlinv_c64* d_xhat, nlinv_c64* d_coils, float* d_img) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_coils, "d_coils", true));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img", true));
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  float2* co = d_coils ? reinterpret_cast<float2*>(d_coils) : plan->w.CO;
+  NLV_CHECK(coils_into(plan, xh, co));
+  if (d_img) NLV_HIP(plan, nlv::launch_image(plan->s, plan->stream, xh, co, d_img));
+  return NLINV_OK;
+}
+
+int nlinv_sync(nlinv_plan plan) {
+  NLV_CHECK(check_plan(plan));
+  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+  NLV_HIP(plan, hipGetLastError());
+  return NLINV_OK;
+}
+
+const char* nlinv_last_error(nlinv_plan plan) {
+  return plan ? plan->err.c_str() : g_err.c_str();
+}
+
+int nlinv_timer_enable(nlinv_plan plan, int32_t kernel_id) {
+  NLV_CHECK(check_plan(plan));
+  if (kernel_id < NLINV_KT_NONE || kernel_id > NLINV_KT_GRID) return fail(plan, NLINV_E_ARG, "unknown kernel id");
+  plan->timer_kid = kernel_id;
+  plan->ev_used = 0;
+  return NLINV_OK;
+}
+
+int nlinv_timer_read(nlinv_plan plan, double* ms, int64_t* launches) {
+  NLV_CHECK(check_plan(plan));
+  if (!ms || !launches) return fail(plan, NLINV_E_ARG, "output pointer is NULL");
+  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < plan->ev_used; i += 2) {
+    float t = 0.f;
+    NLV_HIP(plan, hipEventElapsedTime(&t, plan->ev[i], plan->ev[i + 1]));
+    total += t;
+  }
+  *ms = total;
+  *launches = (int64_t)(plan->ev_used / 2);
+  plan->ev_used = 0;
+  return NLINV_OK;
+}
+
+}  // extern "C"

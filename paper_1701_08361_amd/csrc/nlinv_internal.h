@@ -1,0 +1,106 @@
+// Internal interface between the C-ABI (nlinv_abi.cpp) and the HIP kernel
+// launchers.  Not part of the public API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nlv {
+
+constexpr int ROWS = 8;       // lines per block in the row (x) passes
+constexpr int TW = 8;         // columns per block in the column (y) passes (8 x 16 B = 128 B)
+constexpr int CHUNK = 2048;   // vector elements per block in the CG kernels
+constexpr int VT = 256;       // threads per block in the vector / NUDFT kernels
+constexpr int MAXB = 64;      // largest batch (turn table passed by value)
+
+struct TurnArgs { int32_t t[MAXB]; };
+
+// FP64 partial sums of one scalar, per batch item: p[b * stride + slot].
+struct Partials {
+  const double* cur;  int ncur;    // partials of rr_i = <r_i, r_i>
+  const double* prev; int nprev;   // partials of rr_{i-1}
+  int stride;
+};
+
+// Sizes shared by all launches of a plan.
+struct Shape {
+  int B, J, G, R, GC, S, U;
+  long long X;         // unknowns per item
+  int NT;              // column tiles per channel (R / TW)
+  int NX3;             // coil-adjoint row blocks per item (J * GC / ROWS)
+  int NY2;             // back-column blocks per item (J * NT)
+  int NCI;             // rho-block chunks (ceil(R*R / CHUNK))
+  int NCH;             // vector chunks (ceil(X / CHUNK))
+  int stride;          // partial slots per item
+  bool fast;           // U2 stored in float32 instead of float64
+};
+
+// Device buffers carved from the caller's workspace.
+struct Bufs {
+  double2* tw;    // [G] twiddles (cos, sin)(2 pi m / G)
+  float* dinv;    // [GC][GC] 1 / (G w(kappa))
+  float* P;       // [U][G][G] PSF kernel / (G^2 R^2), natural DFT order
+  double2* psf;   // [G][G] scratch for the PSF build
+  float2* CO;     // [B][J][R][R] coil images c_j
+  double2* U1;    // [B][J][GC][R] coil-spectrum lines (also the adjoint output)
+  void* U2;       // [B][J][G][R] half-transformed grid, double2 (or float2 when fast)
+  float2* PR;     // [B][J][R][R] per-channel conj(c_j) t_j
+  float2* IMG;    // [B][J][R][R] image-space scratch
+  double2* H;     // [B][X] CG iterate increment h
+  double2* Rv;    // [B][X] CG residual r
+  double2* Pv[2]; // [B][X] CG directions p (ping-pong)
+  double2* Q;     // [B][X] operator output (coil block)
+  double* pq;     // [B][stride]
+  double* rr[2];  // [B][stride] ping-pong
+};
+
+// Grid-size specific launchers (one table per supported G).
+struct GTable {
+  // coil spectra of the float32 unknowns -> U1 (W^-1 along x)
+  hipError_t (*coil_rows)(const Shape&, const Bufs&, hipStream_t, const float2* src);
+  // same on a float64 CG direction; with rsrc != nullptr the update p = r + beta p_old
+  // is fused (src = p_old, result written to pdst)
+  hipError_t (*coil_rows_cg)(const Shape&, const Bufs&, hipStream_t, const double2* src,
+                             const double2* rsrc, double2* pdst, Partials sc);
+  // column pass on U1.  mode 0: coils c_j -> co, u = rho c_j -> U2 (out may be null)
+  // mode 1: u = c_j d_rho + rho d_c_j -> U2; mode 2: coils -> co, u = rho c_j -> out (image)
+  // mode 3: u = c_j d_rho + rho d_c_j -> out (image).  psrc: float64 direction.
+  hipError_t (*cols_fwd)(const Shape&, const Bufs&, hipStream_t, int mode, float2* co, const float2* xh,
+                         const double2* psrc, const double2* rsrc, double2* pdst, Partials sc, void* out);
+  // row pass: FFT, multiply by the PSF kernel of each item's turn, inverse FFT (in place on U2)
+  hipError_t (*toep_rows)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns);
+  // column pass back: mode 0 normal (dot partials to pq), 1 residual (z - T u), 2 adjoint of an
+  // image-space float32 input.  Writes PR and U1 (as the W^-H column stage).
+  hipError_t (*cols_back)(const Shape&, const Bufs&, hipStream_t, int mode, const void* in,
+                          const float2* co, const float2* xh, const float2* z, const double2* pv,
+                          double alpha);
+  // row pass: W^-H along x.  mode 0: q = W^-H(..) + alpha p -> out (pq partials at slot NY2)
+  // mode 1: b = W^-H(..) - alpha (x - xprev) -> out and out2 (rr[0] partials at slot 0)
+  // mode 2: raw W^-H -> out.
+  hipError_t (*coilh_rows)(const Shape&, const Bufs&, hipStream_t, int mode, const double2* pv,
+                           const float2* xh, const float2* xprev, double alpha, double2* out,
+                           double2* out2);
+  // PSF kernel: 2D FFT of the embedded PSF (w.psf) -> P (real part x scale)
+  hipError_t (*psf_fft)(const Shape&, const Bufs&, hipStream_t, float* P, double scale);
+};
+
+// Table for grid size G, or nullptr if unsupported.
+const GTable* table_for(int G);
+
+// Grid-size independent launchers.
+hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                          const float2* xprev, double alpha);
+hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
+                            const double2* p, Partials rr, float2* xh, double alpha);
+// out (float32 [B][X]) = (sum_j PR_j + alpha p ; Q) ; p may be null
+hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
+                           double alpha, float2* out);
+hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const float2* src);
+hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);
+hipError_t launch_image(const Shape& s, hipStream_t st, const float2* xh, const float2* co, float* img);
+hipError_t launch_grid(const Shape& s, hipStream_t st, const float* traj, const float2* y, float2* z);
+hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
+                            float2* y);
+hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int turn);
+
+}  // namespace nlv

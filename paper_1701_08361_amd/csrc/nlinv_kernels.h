@@ -1,0 +1,485 @@
+// HIP kernels of the NLINV hot path for gfx950 (MI355X), templated on the grid size.
+//
+// The CG operator q = (DF^H DF + alpha) p of the normal-operator equation
+// (Sec. 2.2) is applied per channel j as
+//     d_c_j = W^-1 d_c_hat_j            (coil synthesis: weight, pad, iFFT, crop)
+//     u_j   = c_j d_rho + rho d_c_j     (derivative of the coil product)
+//     t_j   = F^H F u_j                 (PSF convolution: pad, FFT, x P, iFFT, crop)
+//     q_rho = sum_j conj(c_j) t_j + alpha d_rho,   q_c_hat_j = W^-H(conj(rho) t_j) + alpha d_c_hat_j
+// with every 2D FFT split into a row (x) and a column (y) pass and the
+// pointwise steps fused into the pass that holds the data in registers:
+//     coil_rows : x-iFFT of the (weighted) coil spectra            G_c rows  -> U1
+//     cols_fwd  : y-iFFT -> u_j -> y-FFT                            R columns -> U2
+//     toep_rows : x-FFT -> x P -> x-iFFT (in place)                 G rows
+//     cols_back : y-iFFT -> conj(c_j) t_j, conj(rho) t_j -> y-FFT   R columns -> PR, U1
+//     coilh_rows: x-FFT -> x weight (+ alpha p), dot partials       G_c rows
+//     cg_update : channel sum, CG scalars, h and r updates
+// Zero padding and cropping are never materialised: absent inputs are not
+// loaded and unwanted outputs are not stored.
+//
+// Precision: the transforms run in float64 registers and float64 LDS; the
+// half-transformed grid U2 is stored in float64 (default) or float32 (fast
+// plans), the small coil-row buffer U1 in float64, the coil images and the
+// per-channel products in float32.  CG iterates are far more sensitive to
+// rounding that differs from one operator application to the next than to a
+// fixed error of the operator, so the CG state (h, r, p, q) is float64 too.
+// CG scalars stay on the device as FP64 partial sums reduced in a fixed order
+// (deterministic, no atomics).
+#pragma once
+
+#include "nlinv_fft.h"
+#include "nlinv_internal.h"
+
+namespace nlv {
+
+using C = double2;   // arithmetic type of every transform
+
+// ---------------------------------------------------------------------------
+// reductions (FP64, fixed order, valid for blocks that are not whole waves)
+// ---------------------------------------------------------------------------
+
+constexpr int pow2_ceil(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Sum over the block; the result is returned to every thread.  sh: [NT] doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  __syncthreads();   // sh may still be read by a previous call
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = pow2_ceil(NT) / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && (int)threadIdx.x + s < NT) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Sum of p[0..n), returned to every thread.
+template <int NT>
+__device__ __forceinline__ double block_sum_array(const double* __restrict__ p, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+  return block_sum<NT>(s, sh);
+}
+
+template <int NT>
+__device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh) {
+  const double rc = block_sum_array<NT>(sc.cur + (size_t)b * sc.stride, sc.ncur, sh);
+  const double rp = block_sum_array<NT>(sc.prev + (size_t)b * sc.stride, sc.nprev, sh);
+  return rp != 0.0 ? rc / rp : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// coil_rows: W^-1 along x.  Line (b, j, i): G_c weighted coil coefficients of
+// spectrum row i -> R image columns.  Optional fused p = r + beta p_old.
+// ---------------------------------------------------------------------------
+template <int G, class V>
+__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
+            Partials sc, const float* __restrict__ dinv, const double2* __restrict__ tw,
+            double2* __restrict__ U1, int J, long long X) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NTH = ROWS * T::SIZE;
+  __shared__ C lds[ROWS * T::LDSN];
+  __shared__ double sh[NTH];
+  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const int row = blockIdx.x * ROWS + rl;
+  const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
+  const bool upd = rsrc != nullptr;
+  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
+  const size_t off = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
+  const float* dw = dinv + i * GC;
+  C v[T::G1];
+  fsA<G, +1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
+    const int ic = coil_idx<G>(n);
+    if (ic < 0) return czero<C>();
+    double2 p = to_d(src[off + ic]);
+    if (upd) {
+      const double2 r = rsrc[off + ic];
+      p = make_double2(r.x + beta * p.x, r.y + beta * p.y);
+      pdst[off + ic] = p;
+    }
+    return cscale(p, (double)dw[ic]);
+  }, v);
+  if (tl < T::G2) {
+    double2* o = U1 + ((size_t)bj * GC + i) * R;
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int ix = img_idx<G>(T::G2 * k1 + tl);
+      if (ix >= 0) o[ix] = v[k1];
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cols_fwd: W^-1 along y, coil product, forward FFT along y.
+// MODE 0: coils -> co, u = rho c_j -> out (U2, may be null)
+// MODE 1: u = c_j d_rho + rho d_c_j -> out (U2);  MODE 2 / 3: as 0 / 1 but u -> out (image, float32)
+// ---------------------------------------------------------------------------
+template <int G, int MODE, class S2>
+__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2* __restrict__ xh,
+           const double2* __restrict__ psrc, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
+           Partials sc, const double2* __restrict__ tw, void* __restrict__ outp, int J, long long X) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = TW * T::SIZE;
+  constexpr bool NORMAL = (MODE == 1 || MODE == 3);
+  constexpr bool TO_IMG = (MODE == 2 || MODE == 3);
+  __shared__ C lds[TW * T::LDSN];
+  __shared__ double sh[NTH];
+  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
+  const int x = tile * TW + col;
+  C* L = lds + col * T::LDSN;
+  const bool upd = NORMAL && rsrc != nullptr;
+  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
+
+  const double2* u1 = U1 + (size_t)bj * GC * R + x;
+  C v[T::G1];
+  fsA<G, +1>(tl, L, tw, [&](int n) -> C {
+    const int i = coil_idx<G>(n);
+    return i < 0 ? czero<C>() : u1[(size_t)i * R];
+  }, v);
+
+  const float2* rho = xh + (size_t)b * X;
+  float2* cj = co + (size_t)bj * R * R;
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int iy = img_idx<G>(T::G2 * k1 + tl);
+      C u = czero<C>();
+      if (iy >= 0) {
+        const size_t e = (size_t)iy * R + x;
+        const C r = to_d(rho[e]);
+        if constexpr (!NORMAL) {
+          const float2 cf = to_f(v[k1]);
+          cj[e] = cf;
+          u = cmul(r, to_d(cf));   // the stored (float32) coil image, as later passes read it
+        } else {
+          const size_t pe = (size_t)b * X + e;
+          double2 dr = psrc[pe];
+          if (upd) {
+            const double2 rr = rsrc[pe];
+            dr = make_double2(rr.x + beta * dr.x, rr.y + beta * dr.y);
+            if (j == 0) pdst[pe] = dr;
+          }
+          u = cadd(cmul(to_d(cj[e]), dr), cmul(r, v[k1]));
+        }
+        if constexpr (TO_IMG) static_cast<float2*>(outp)[(size_t)bj * R * R + e] = to_f(u);
+      }
+      v[k1] = u;
+    });
+  }
+  if constexpr (!TO_IMG) {
+    if (outp == nullptr) return;   // uniform: coil synthesis only
+    S2* o = static_cast<S2*>(outp) + (size_t)bj * G * R + x;
+    fsB<G, -1>(tl, L, tw, v, [&](int n, C val) { o[(size_t)n * R] = store_as<S2>(val); });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// toep_rows: along x, FFT (R inputs) -> x P(ky, kx) -> iFFT (R outputs), in place.
+// ---------------------------------------------------------------------------
+template <int G, class S2>
+__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
+            const double2* __restrict__ tw, int J) {
+  using T = Team<G>;
+  constexpr int R = G / 2;
+  __shared__ C lds[ROWS * T::LDSN];
+  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const int row = blockIdx.x * ROWS + rl;
+  const int ky = row % G, b = row / G / J;
+  S2* line = U2 + (size_t)row * R;
+  const float* prow = P + ((size_t)turns.t[b] * G + ky) * G;
+  C* L = lds + rl * T::LDSN;
+  C v[T::G1];
+  fsA<G, -1>(tl, L, tw, [&](int n) -> C {
+    const int ix = img_idx<G>(n);
+    return ix < 0 ? czero<C>() : to_d(line[ix]);
+  }, v);
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      v[k1] = cscale(v[k1], (double)prow[T::G2 * k1 + tl]);
+    });
+  }
+  fsB<G, +1>(tl, L, tw, v, [&](int n, C val) {
+    const int ix = img_idx<G>(n);
+    if (ix >= 0) line[ix] = store_as<S2>(val);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// cols_back: iFFT along y (or an image-space input), channel terms, FFT along y
+// to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32).
+// ---------------------------------------------------------------------------
+template <int G, int MODE, class S2>
+__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
+            const float2* __restrict__ z, const double2* __restrict__ pv, double alpha,
+            const double2* __restrict__ tw, float2* __restrict__ PR, double2* __restrict__ U4,
+            double* __restrict__ part, int stride, int J, long long X) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = TW * T::SIZE;
+  __shared__ C lds[TW * T::LDSN];
+  __shared__ double sh[NTH];
+  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
+  const int x = tile * TW + col;
+  C* L = lds + col * T::LDSN;
+  const size_t img = (size_t)bj * R * R;
+
+  C v[T::G1];
+  if constexpr (MODE != 2) {
+    const S2* c0 = static_cast<const S2*>(inp) + (size_t)bj * G * R + x;
+    fsA<G, +1>(tl, L, tw, [&](int n) -> C { return to_d(c0[(size_t)n * R]); }, v);
+  } else {
+    const float2* in = static_cast<const float2*>(inp);
+    if (tl < T::G2) {
+      sfor<0, T::G1>([&](auto c) {
+        constexpr int k1 = decltype(c)::value;
+        const int iy = img_idx<G>(T::G2 * k1 + tl);
+        v[k1] = iy < 0 ? czero<C>() : to_d(in[img + (size_t)iy * R + x]);
+      });
+    }
+  }
+
+  const float2* rho = xh + (size_t)b * X;
+  double dot = 0.0;
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int iy = img_idx<G>(T::G2 * k1 + tl);
+      C s = czero<C>();
+      if (iy >= 0) {
+        const size_t e = (size_t)iy * R + x;
+        C t = v[k1];
+        if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
+        const float2 prf = to_f(cjmul(to_d(co[img + e]), t));
+        PR[img + e] = prf;
+        if constexpr (MODE == 0) {
+          const double2 dr = pv[(size_t)b * X + e];
+          dot += dr.x * prf.x + dr.y * prf.y;
+          if (j == 0) dot += alpha * (dr.x * dr.x + dr.y * dr.y);
+        }
+        s = cjmul(to_d(rho[e]), t);
+      }
+      v[k1] = s;
+    });
+  }
+  double2* o = U4 + (size_t)bj * GC * R + x;
+  fsB<G, -1>(tl, L, tw, v, [&](int n, C val) {
+    const int i = coil_idx<G>(n);
+    if (i >= 0) o[(size_t)i * R] = val;
+  });
+  if constexpr (MODE == 0) {
+    const double s = block_sum<NTH>(dot, sh);
+    if (threadIdx.x == 0) part[(size_t)b * stride + j * NT + tile] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coilh_rows: W^-H along x plus the regularisation term.
+// MODE 0: q = W^-H(.) + alpha p  (partials Re<p, q> -> part at slot_off)
+// MODE 1: b = W^-H(.) - alpha (x - x_prev) -> out, out2 (partials |b|^2)
+// MODE 2: raw W^-H(.) -> out
+// ---------------------------------------------------------------------------
+template <int G, int MODE>
+__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
+             const double2* __restrict__ pv, const float2* __restrict__ xh, const float2* __restrict__ xprev,
+             double alpha, double2* __restrict__ out, double2* __restrict__ out2,
+             double* __restrict__ part, int stride, int slot_off, int J, long long X) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NTH = ROWS * T::SIZE;
+  __shared__ C lds[ROWS * T::LDSN];
+  __shared__ double sh[NTH];
+  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const int row = blockIdx.x * ROWS + rl;
+  const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
+  const double2* line = U4 + (size_t)row * R;
+  C v[T::G1];
+  fsA<G, -1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
+    const int ix = img_idx<G>(n);
+    return ix < 0 ? czero<C>() : line[ix];
+  }, v);
+  double acc = 0.0;
+  if (tl < T::G2) {
+    const size_t base = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
+    const float* dw = dinv + i * GC;
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int ic = coil_idx<G>(T::G2 * k1 + tl);
+      if (ic >= 0) {
+        const size_t e = base + ic;
+        const double2 wv = cscale(v[k1], (double)dw[ic]);
+        if constexpr (MODE == 0) {
+          const double2 p = pv[e];
+          const double2 q = make_double2(wv.x + alpha * p.x, wv.y + alpha * p.y);
+          out[e] = q;
+          acc += p.x * q.x + p.y * q.y;
+        } else if constexpr (MODE == 1) {
+          const float2 xv = xh[e];
+          const float2 xp = xprev ? xprev[e] : make_float2(0.f, 0.f);
+          const double2 bv = make_double2(wv.x - alpha * ((double)xv.x - xp.x),
+                                          wv.y - alpha * ((double)xv.y - xp.y));
+          out[e] = bv;
+          out2[e] = bv;
+          acc += bv.x * bv.x + bv.y * bv.y;
+        } else {
+          out[e] = wv;
+        }
+      }
+    });
+  }
+  if constexpr (MODE != 2) {
+    const double s = block_sum<NTH>(acc, sh);
+    const int blocal = blockIdx.x - b * (J * GC / ROWS);
+    if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + blocal] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PSF kernel: full forward 2D FFT of the embedded PSF (float64 scratch)
+// ---------------------------------------------------------------------------
+
+// Full G-point FFT along the rows of a G x G array (in place), forward.
+template <int G>
+__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+k_fft_rows_full(double2* __restrict__ a, const double2* __restrict__ tw) {
+  using T = Team<G>;
+  __shared__ C lds[ROWS * T::LDSN];
+  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const int row = blockIdx.x * ROWS + rl;
+  double2* line = a + (size_t)row * G;
+  C v[T::G1];
+  fsA<G, -1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C { return line[n]; }, v);
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      line[T::G2 * k1 + tl] = v[k1];
+    });
+  }
+}
+
+// Full forward FFT along the columns; P[ky][kx] = Re(.) * scale (float32).
+template <int G>
+__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const double2* __restrict__ tw,
+               double scale) {
+  using T = Team<G>;
+  __shared__ C lds[TW * T::LDSN];
+  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const int x = blockIdx.x * TW + col;
+  C v[T::G1];
+  fsA<G, -1>(tl, lds + col * T::LDSN, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      P[(size_t)(T::G2 * k1 + tl) * G + x] = (float)(v[k1].x * scale);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-grid launch table
+// ---------------------------------------------------------------------------
+
+template <int G>
+struct GLaunch {
+  static constexpr int TH_ROWS = ROWS * Team<G>::SIZE;
+  static constexpr int TH_COLS = TW * Team<G>::SIZE;
+
+  static hipError_t coil_rows(const Shape& s, const Bufs& w, hipStream_t st, const float2* src) {
+    k_coil_rows<G, float2><<<s.B * s.J * s.GC / ROWS, TH_ROWS, 0, st>>>(src, nullptr, nullptr, Partials{},
+                                                                          w.dinv, w.tw, w.U1, s.J, s.X);
+    return hipGetLastError();
+  }
+  static hipError_t coil_rows_cg(const Shape& s, const Bufs& w, hipStream_t st, const double2* src,
+                                 const double2* rsrc, double2* pdst, Partials sc) {
+    k_coil_rows<G, double2><<<s.B * s.J * s.GC / ROWS, TH_ROWS, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
+                                                                           w.tw, w.U1, s.J, s.X);
+    return hipGetLastError();
+  }
+  template <class S2>
+  static hipError_t cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
+                               const float2* xh, const double2* psrc, const double2* rsrc, double2* pdst,
+                               Partials sc, void* out) {
+    const int blocks = s.B * s.J * s.NT;
+    switch (mode) {
+      case 0: k_cols_fwd<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
+      case 1: k_cols_fwd<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
+      case 2: k_cols_fwd<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
+      case 3: k_cols_fwd<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  static hipError_t cols_fwd(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
+                             const float2* xh, const double2* psrc, const double2* rsrc, double2* pdst,
+                             Partials sc, void* out) {
+    return s.fast ? cols_fwd_t<float2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out)
+                  : cols_fwd_t<double2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out);
+  }
+  static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
+    const int blocks = s.B * s.J * s.G / ROWS;
+    if (s.fast)
+      k_toep_rows<G, float2><<<blocks, TH_ROWS, 0, st>>>(static_cast<float2*>(w.U2), w.P, turns, w.tw, s.J);
+    else
+      k_toep_rows<G, double2><<<blocks, TH_ROWS, 0, st>>>(static_cast<double2*>(w.U2), w.P, turns, w.tw, s.J);
+    return hipGetLastError();
+  }
+  template <class S2>
+  static hipError_t cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
+                                const float2* co, const float2* xh, const float2* z, const double2* pv,
+                                double alpha) {
+    const int blocks = s.B * s.J * s.NT;
+    switch (mode) {
+      case 0: k_cols_back<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
+      case 1: k_cols_back<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
+      case 2: k_cols_back<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  static hipError_t cols_back(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
+                              const float2* co, const float2* xh, const float2* z, const double2* pv,
+                              double alpha) {
+    return s.fast ? cols_back_t<float2>(s, w, st, mode, in, co, xh, z, pv, alpha)
+                  : cols_back_t<double2>(s, w, st, mode, in, co, xh, z, pv, alpha);
+  }
+  static hipError_t coilh_rows(const Shape& s, const Bufs& w, hipStream_t st, int mode, const double2* pv,
+                               const float2* xh, const float2* xprev, double alpha, double2* out,
+                               double2* out2) {
+    const int blocks = s.B * s.J * s.GC / ROWS;
+    double* part = mode == 1 ? w.rr[0] : w.pq;
+    const int off = mode == 0 ? s.NY2 : 0;
+    switch (mode) {
+      case 0: k_coilh_rows<G, 0><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
+      case 1: k_coilh_rows<G, 1><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
+      case 2: k_coilh_rows<G, 2><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  static hipError_t psf_fft(const Shape& s, const Bufs& w, hipStream_t st, float* P, double scale) {
+    k_fft_rows_full<G><<<G / ROWS, TH_ROWS, 0, st>>>(w.psf, w.tw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_fft_cols_psf<G><<<G / TW, TH_COLS, 0, st>>>(w.psf, P, w.tw, scale);
+    return hipGetLastError();
+  }
+};
+
+template <int G>
+constexpr GTable make_table() {
+  return GTable{&GLaunch<G>::coil_rows, &GLaunch<G>::coil_rows_cg, &GLaunch<G>::cols_fwd,
+                &GLaunch<G>::toep_rows, &GLaunch<G>::cols_back, &GLaunch<G>::coilh_rows,
+                &GLaunch<G>::psf_fft};
+}
+
+}  // namespace nlv

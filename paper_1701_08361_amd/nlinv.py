@@ -1,0 +1,302 @@
+"""Thin ctypes binding of libnlinv.so (the C-ABI declared in include/nlinv.h).
+
+Argument marshalling only: tensors are checked for device, dtype, shape and
+contiguity and their data pointers are passed to the library, which enqueues
+its HIP kernels on torch's current stream.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnlinv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nlinv.h")
+
+OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5
+KT = {"none": 0, "toeplitz_rows": 1, "coil_cols": 2, "back_cols": 3, "cg_update": 4,
+      "coil_rows": 5, "coilh_rows": 6, "grid": 7}
+
+
+class NlinvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nlinv error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("G", ctypes.c_int32), ("J", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("S_r", ctypes.c_int32), ("U", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("newton", ctypes.c_int32), ("cg", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("alpha0", ctypes.c_double), ("alpha_q", ctypes.c_double),
+                ("alpha_min", ctypes.c_double), ("sob_a", ctypes.c_double), ("sob_l", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+
+
+def load() -> ctypes.CDLL:
+    """Load libnlinv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} not built: run `python -m paper_1701_08361_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "nlinv_params_default": [ctypes.POINTER(Params)],
+        "nlinv_workspace_size": [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
+        "nlinv_sizes": [ctypes.POINTER(Params), _P, _P, _P, _P, _P],
+        "nlinv_plan_create": [ctypes.POINTER(Params), _P, _P, ctypes.c_size_t, ctypes.POINTER(_P)],
+        "nlinv_plan_destroy": [_P],
+        "nlinv_set_stream": [_P, _P],
+        "nlinv_psf": [_P, _P, _I],
+        "nlinv_grid": [_P, _P, _P, _P, _P],
+        "nlinv_reconstruct": [_P, _P, _P, _P, _P, _I, _P, _P],
+        "nlinv_apply_F": [_P, _P, _P, _P],
+        "nlinv_apply_DF": [_P, _P, _P, _P, _P],
+        "nlinv_apply_DFH": [_P, _P, _P, _P, _P],
+        "nlinv_apply_normal": [_P, _P, _P, ctypes.c_double, _P, _P],
+        "nlinv_coils": [_P, _P, _P, _P],
+        "nlinv_sync": [_P],
+        "nlinv_timer_enable": [_P, _I],
+        "nlinv_timer_read": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.nlinv_last_error.argtypes = [_P]
+    lib.nlinv_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list:
+    """Names of the functions declared in include/nlinv.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(nlinv_\w+)\s*\(", text, re.M)))
+
+
+def _check(rc: int, plan=None):
+    if rc != OK:
+        msg = load().nlinv_last_error(plan)
+        raise NlinvError(rc, msg.decode() if msg else "")
+
+
+def make_params(N: int, J: int, K: int, S_r: int = 0, U: int = 1, batch: int = 1, newton: int = 7,
+                cg: int = 10, alpha0: float = 1.0, alpha_q: float = 0.5, alpha_min: float = 0.0,
+                G: int = 0, sob_a: float = 880.0, sob_l: float = 16.0, flags: int = 0) -> Params:
+    p = Params()
+    _check(load().nlinv_params_default(ctypes.byref(p)))
+    p.N, p.G, p.J, p.K, p.S_r, p.U, p.batch = N, G, J, K, S_r, U, batch
+    p.newton, p.cg, p.flags = newton, cg, flags
+    p.alpha0, p.alpha_q, p.alpha_min, p.sob_a, p.sob_l = alpha0, alpha_q, alpha_min, sob_a, sob_l
+    return p
+
+
+def workspace_size(p: Params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().nlinv_workspace_size(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def sizes(p: Params) -> dict:
+    R, G, Gc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    S, X = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().nlinv_sizes(ctypes.byref(p), ctypes.byref(R), ctypes.byref(G), ctypes.byref(Gc),
+                              ctypes.byref(S), ctypes.byref(X)))
+    return {"R": R.value, "G": G.value, "Gc": Gc.value, "S": S.value, "X": X.value}
+
+
+class Plan:
+    """One NLINV plan: sizes, FP64 tables and a device workspace (a torch tensor)."""
+
+    def __init__(self, N: int, J: int, K: int, device="cuda", **kw):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.params = make_params(N, J, K, **kw)
+        sz = sizes(self.params)
+        self.N, self.J, self.K = N, J, K
+        self.R, self.G, self.Gc, self.S, self.X = sz["R"], sz["G"], sz["Gc"], sz["S"], sz["X"]
+        self.B = self.params.batch
+        self.U = self.params.U
+        self.S_r = self.S // K
+        self.device = torch.device(device)
+        nbytes = workspace_size(self.params)
+        self.ws_bytes = nbytes
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes]
+        self._stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = _P()
+        _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
+                                          _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
+        self.handle = h
+
+    # -- helpers ---------------------------------------------------------
+    def _stream_sync(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            _check(self.lib.nlinv_set_stream(self.handle, _P(s)), self.handle)
+            self._stream = s
+
+    def _t(self, t, dtype, shape, name, allow_none=False):
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        if t.device != self.device and not (t.is_cuda and self.device.type == "cuda"):
+            raise ValueError(f"{name} must be on {self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def _ptr(self, t):
+        return _P(t.data_ptr()) if t is not None else _P()
+
+    def _turns(self, turns):
+        if turns is None:
+            return None
+        if isinstance(turns, int):
+            turns = [turns] * self.B
+        if len(turns) != self.B:
+            raise ValueError("one turn per batch item")
+        return (ctypes.c_int32 * self.B)(*[int(t) for t in turns])
+
+    def empty(self, *shape, dtype=None):
+        return self.torch.empty(*shape, dtype=dtype or self.torch.complex64, device=self.device)
+
+    # -- API -------------------------------------------------------------
+    def psf(self, traj, turn: int):
+        torch = self.torch
+        self._t(traj, torch.float32, (self.K, self.S_r, 2), "traj")
+        self._stream_sync()
+        _check(self.lib.nlinv_psf(self.handle, self._ptr(traj), int(turn)), self.handle)
+
+    def grid(self, traj, y, turns: Optional[Sequence[int]] = None, z=None):
+        torch = self.torch
+        B, J, R = self.B, self.J, self.R
+        self._t(traj, torch.float32, (B, self.K, self.S_r, 2), "traj")
+        self._t(y, torch.complex64, (B, J, self.S), "y")
+        if z is None:
+            z = self.empty(B, J, R, R)
+        self._t(z, torch.complex64, (B, J, R, R), "z")
+        self._stream_sync()
+        _check(self.lib.nlinv_grid(self.handle, self._ptr(traj), self._ptr(y), self._turns(turns),
+                                   self._ptr(z)), self.handle)
+        return z
+
+    def reconstruct(self, z, turns, xprev=None, xhat=None, init: Optional[int] = None, img=None,
+                    coils=None, want_img: bool = False, want_coils: bool = False):
+        torch = self.torch
+        B, J, R, X = self.B, self.J, self.R, self.X
+        self._t(z, torch.complex64, (B, J, R, R), "z")
+        self._t(xprev, torch.complex64, (B, X), "xprev", allow_none=True)
+        if xhat is None:
+            xhat = self.empty(B, X)
+            if init is None:
+                init = 2 if xprev is not None else 1
+        elif init is None:
+            init = 0
+        self._t(xhat, torch.complex64, (B, X), "xhat")
+        if want_img and img is None:
+            img = self.empty(B, R, R, dtype=torch.float32)
+        if want_coils and coils is None:
+            coils = self.empty(B, J, R, R)
+        self._t(img, torch.float32, (B, R, R), "img", allow_none=True)
+        self._t(coils, torch.complex64, (B, J, R, R), "coils", allow_none=True)
+        self._stream_sync()
+        _check(self.lib.nlinv_reconstruct(self.handle, self._ptr(z), self._turns(turns), self._ptr(xprev),
+                                          self._ptr(xhat), int(init), self._ptr(img), self._ptr(coils)),
+               self.handle)
+        return xhat, img, coils
+
+    def apply_F(self, traj, xhat, y=None):
+        torch = self.torch
+        self._t(traj, torch.float32, (self.B, self.K, self.S_r, 2), "traj")
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        y = self.empty(self.B, self.J, self.S) if y is None else y
+        self._t(y, torch.complex64, (self.B, self.J, self.S), "y")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_F(self.handle, self._ptr(traj), self._ptr(xhat), self._ptr(y)), self.handle)
+        return y
+
+    def apply_DF(self, traj, xhat, dx, dy=None):
+        torch = self.torch
+        self._t(traj, torch.float32, (self.B, self.K, self.S_r, 2), "traj")
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(dx, torch.complex64, (self.B, self.X), "dx")
+        dy = self.empty(self.B, self.J, self.S) if dy is None else dy
+        self._t(dy, torch.complex64, (self.B, self.J, self.S), "dy")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_DF(self.handle, self._ptr(traj), self._ptr(xhat), self._ptr(dx),
+                                       self._ptr(dy)), self.handle)
+        return dy
+
+    def apply_DFH(self, traj, xhat, dy, dx=None):
+        torch = self.torch
+        self._t(traj, torch.float32, (self.B, self.K, self.S_r, 2), "traj")
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(dy, torch.complex64, (self.B, self.J, self.S), "dy")
+        dx = self.empty(self.B, self.X) if dx is None else dx
+        self._t(dx, torch.complex64, (self.B, self.X), "dx")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_DFH(self.handle, self._ptr(traj), self._ptr(xhat), self._ptr(dy),
+                                        self._ptr(dx)), self.handle)
+        return dx
+
+    def apply_normal(self, turns, xhat, p, alpha: float = 0.0, q=None):
+        torch = self.torch
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(p, torch.complex64, (self.B, self.X), "p")
+        q = self.empty(self.B, self.X) if q is None else q
+        self._t(q, torch.complex64, (self.B, self.X), "q")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_normal(self.handle, self._turns(turns), self._ptr(xhat), float(alpha),
+                                           self._ptr(p), self._ptr(q)), self.handle)
+        return q
+
+    def coils(self, xhat, coils=None, img=None, want_img: bool = True):
+        torch = self.torch
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        coils = self.empty(self.B, self.J, self.R, self.R) if coils is None else coils
+        if want_img and img is None:
+            img = self.empty(self.B, self.R, self.R, dtype=torch.float32)
+        self._stream_sync()
+        _check(self.lib.nlinv_coils(self.handle, self._ptr(xhat), self._ptr(coils), self._ptr(img)), self.handle)
+        return coils, img
+
+    def timer_enable(self, kernel: str):
+        _check(self.lib.nlinv_timer_enable(self.handle, KT[kernel]), self.handle)
+
+    def timer_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.nlinv_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n)), self.handle)
+        return ms.value, n.value
+
+    def sync(self):
+        _check(self.lib.nlinv_sync(self.handle), self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.nlinv_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,85 @@
+"""Host-side checks of the C-ABI: the library loads, exports every symbol that
+include/nlinv.h declares, and validates arguments before touching a device.
+No test here launches a kernel or needs a GPU."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1701_08361_amd import nlinv as nl
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nl.LIB_PATH):
+        from paper_1701_08361_amd import build
+        build.build(verbose=False)
+    return nl.load()
+
+
+def test_exports_every_header_symbol(lib):
+    names = nl.header_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in nlinv.h but not exported"
+
+
+@pytest.mark.parametrize("N,J,K,expect", [
+    (64, 8, 13, dict(R=64, G=128, Gc=32, S=13 * 128, X=64 * 64 + 8 * 32 * 32)),
+    (160, 10, 15, dict(R=160, G=320, Gc=80, S=15 * 320, X=160 * 160 + 10 * 80 * 80)),
+    (224, 16, 21, dict(R=224, G=448, Gc=112, S=21 * 448, X=224 * 224 + 16 * 112 * 112)),
+])
+def test_sizes(lib, N, J, K, expect):
+    p = nl.make_params(N, J, K)
+    assert nl.sizes(p) == expect
+    assert nl.workspace_size(p) > 0
+
+
+def test_workspace_grows_with_batch(lib):
+    a = nl.workspace_size(nl.make_params(160, 10, 15, batch=1))
+    b = nl.workspace_size(nl.make_params(160, 10, 15, batch=16))
+    assert 10 * a < b < 17 * a
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=100, J=8, K=13), nl.E_SIZE),           # G = 200 unsupported
+    (dict(N=64, J=8, K=13, G=192), nl.E_SIZE),     # gamma != 1
+    (dict(N=64, J=8, K=14), nl.E_ARG),             # even spoke count
+    (dict(N=64, J=0, K=13), nl.E_ARG),
+    (dict(N=64, J=65, K=13), nl.E_ARG),
+    (dict(N=64, J=8, K=13, batch=0), nl.E_ARG),
+    (dict(N=64, J=8, K=13, batch=65), nl.E_ARG),
+    (dict(N=64, J=8, K=13, U=0), nl.E_ARG),
+    (dict(N=64, J=8, K=13, cg=0), nl.E_ARG),
+    (dict(N=64, J=8, K=13, flags=2), nl.E_ARG),   # unknown flag bit
+    (dict(N=64, J=8, K=13, alpha0=0.0), nl.E_ARG),
+    (dict(N=64, J=8, K=13, alpha_q=1.5), nl.E_ARG),
+    (dict(N=64, J=8, K=13, alpha_min=-1.0), nl.E_ARG),
+    (dict(N=0, J=8, K=13), nl.E_ARG),
+])
+def test_invalid_params_rejected(lib, kw, code):
+    p = nl.make_params(**kw)
+    with pytest.raises(nl.NlinvError) as ei:
+        nl.workspace_size(p)
+    assert ei.value.code == code
+    assert len(lib.nlinv_last_error(None)) > 0
+
+
+def test_plan_create_checks_workspace_before_any_device_call(lib):
+    p = nl.make_params(64, 8, 13)
+    need = nl.workspace_size(p)
+    h = ctypes.c_void_p()
+    rc = lib.nlinv_plan_create(ctypes.byref(p), None, None, need, ctypes.byref(h))
+    assert rc == nl.E_WORKSPACE and not h.value
+    rc = lib.nlinv_plan_create(ctypes.byref(p), None, ctypes.c_void_p(1 << 20), need - 1, ctypes.byref(h))
+    assert rc == nl.E_WORKSPACE
+    rc = lib.nlinv_plan_create(ctypes.byref(p), None, ctypes.c_void_p((1 << 20) + 8), need, ctypes.byref(h))
+    assert rc == nl.E_WORKSPACE and b"aligned" in lib.nlinv_last_error(None)
+    assert lib.nlinv_plan_create(ctypes.byref(p), None, None, 0, None) == nl.E_ARG
+
+
+def test_null_plan_rejected(lib):
+    assert lib.nlinv_sync(None) == nl.E_ARG
+    assert lib.nlinv_reconstruct(None, None, None, None, None, 1, None, None) == nl.E_ARG
+    assert lib.nlinv_grid(None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_plan_destroy(None) == nl.E_ARG

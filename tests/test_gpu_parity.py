@@ -1,0 +1,269 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances: relative L2 error <= 1e-4 for every operator application and
+<= 1e-3 on the final image |rho| sqrt(sum |c_j|^2) and on the gauge-invariant
+coil images rho c_j after a fixed number of Newton steps.  Inputs are the
+seeded synthetic series of the generator; nothing is read from stored GPU
+output.
+"""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1701_08361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-4
+IMG_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1701_08361_amd import nlinv
+    nlinv.load()            # fails loudly when the HIP library is missing
+    return _t
+
+
+def nl():
+    from paper_1701_08361_amd import nlinv
+    return nlinv
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def random_point(seed, g, c_scale=1.0):
+    """x_hat with O(1) image and coil spectra (complex64)."""
+    return synth.random_xhat(seed, g.R, g.J, g.Gc, 1.0, c_scale)
+
+
+def print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# gridding, coils, PSF convolution
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,J,K,seed", [(32, 3, 5, 11), (64, 8, 13, 1), (160, 10, 15, 2)])
+def test_grid_matches_exact_adjoint_nudft(torch, N, J, K, seed):
+    print_case("grid", N=N, J=J, K=K, seed=seed)
+    s = synth.single_frame(seed=seed, N=N, J=J, K=K)
+    plan = nl().Plan(N, J, K)
+    z = host(plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0]))
+    ref = O.grid(s.y[0], s.traj[0], plan.R)
+    print(f"grid rel {rel(z[0], ref):.2e}")
+    assert rel(z[0], ref) < OP_TOL
+
+
+@pytest.mark.parametrize("N,J", [(32, 2), (64, 8), (128, 5), (160, 10), (192, 3), (224, 4)])
+def test_coil_synthesis(torch, N, J):
+    print_case("coils", N=N, J=J)
+    plan = nl().Plan(N, J, 5)
+    g = O.Geometry.make(N, J)
+    x = random_point(100 + N, g)
+    co, img = plan.coils(dev(torch, x[None]))
+    ref = g.coils(x)
+    assert rel(host(co)[0], ref) < OP_TOL
+    assert rel(host(img)[0], O.image(g, x)) < OP_TOL
+
+
+def _normal_case(torch, N, J, K, U, B, alpha, seed):
+    plan = nl().Plan(N, J, K, U=U, batch=B)
+    g = O.Geometry.make(N, J)
+    trajs = [synth.radial_trajectory(N, K, 2 * N, t, U) for t in range(U)]
+    for t in range(U):
+        plan.psf(dev(torch, trajs[t]), t)
+    turns = [(b * 2 + 1) % U for b in range(B)]
+    xs = np.stack([random_point(seed + b, g) for b in range(B)])
+    ps = np.stack([random_point(seed + 50 + b, g) for b in range(B)])
+    q = host(plan.apply_normal(turns, dev(torch, xs), dev(torch, ps), alpha=alpha))
+    R2 = g.R * g.R
+    for b in range(B):
+        P = O.psf_kernel(trajs[turns[b]], g.R, g.G)
+        ref = O.normal(g, xs[b], ps[b], P) + alpha * ps[b].astype(np.complex128)
+        print(f"normal item {b}: image block rel {rel(q[b, :R2], ref[:R2]):.2e}  "
+              f"coil block rel {rel(q[b, R2:], ref[R2:]):.2e}")
+        assert rel(q[b, :R2], ref[:R2]) < OP_TOL, "image block"
+        assert rel(q[b, R2:], ref[R2:]) < OP_TOL, "coil block"
+        # scale-free check of every coil coefficient (undo the Sobolev weight)
+        if alpha == 0.0:
+            w = np.tile(g.w.ravel(), J)
+            assert rel(q[b, R2:] * w, ref[R2:] * w) < OP_TOL, "weighted coil block"
+
+
+@pytest.mark.parametrize("N,J,K,U,B,alpha", [
+    (32, 2, 5, 1, 1, 0.0), (64, 8, 13, 2, 3, 0.37), (64, 8, 13, 1, 1, 0.0),
+    (128, 4, 11, 3, 2, 0.0), (160, 10, 15, 5, 2, 0.125), (192, 3, 9, 1, 1, 0.0),
+    (224, 5, 21, 2, 2, 0.5)])
+def test_normal_operator(torch, N, J, K, U, B, alpha):
+    print_case("normal", N=N, J=J, K=K, U=U, B=B, alpha=alpha)
+    _normal_case(torch, N, J, K, U, B, alpha, seed=7 * N + J)
+
+
+# ---------------------------------------------------------------------------
+# operators on radial samples
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,J,K,B", [(32, 2, 5, 1), (64, 8, 13, 2), (160, 10, 15, 1)])
+def test_F_DF_DFH_match_oracle(torch, N, J, K, B):
+    print_case("F/DF/DFH", N=N, J=J, K=K, B=B)
+    plan = nl().Plan(N, J, K, batch=B)
+    g = O.Geometry.make(N, J)
+    trajs = np.stack([synth.radial_trajectory(N, K, 2 * N, b, 3) for b in range(B)])
+    xs = np.stack([random_point(300 + b, g) for b in range(B)])
+    dxs = np.stack([random_point(400 + b, g) for b in range(B)])
+    vs = np.stack([synth.random_samples(500 + b, J, plan.S) for b in range(B)])
+    tr = dev(torch, trajs)
+    Fx = host(plan.apply_F(tr, dev(torch, xs)))
+    DFu = host(plan.apply_DF(tr, dev(torch, xs), dev(torch, dxs)))
+    DFHv = host(plan.apply_DFH(tr, dev(torch, xs), dev(torch, vs)))
+    R2 = g.R * g.R
+    for b in range(B):
+        assert rel(Fx[b], O.F_hat(g, xs[b], trajs[b])) < OP_TOL
+        assert rel(DFu[b], O.DF_hat(g, xs[b], dxs[b], trajs[b])) < OP_TOL
+        ref = O.DFH_hat(g, xs[b], vs[b], trajs[b])
+        assert rel(DFHv[b, :R2], ref[:R2]) < OP_TOL
+        assert rel(DFHv[b, R2:], ref[R2:]) < OP_TOL
+
+
+def test_gpu_DF_DFH_are_adjoint(torch):
+    N, J, K = 64, 4, 9
+    plan = nl().Plan(N, J, K)
+    g = O.Geometry.make(N, J)
+    tr = dev(torch, synth.radial_trajectory(N, K, 2 * N, 0, 1)[None])
+    x = dev(torch, random_point(1, g)[None])
+    u = dev(torch, random_point(2, g)[None])
+    v = dev(torch, synth.random_samples(3, J, plan.S)[None])
+    lhs = torch.vdot(plan.apply_DF(tr, x, u).ravel().to(torch.complex128), v.ravel().to(torch.complex128))
+    rhs = torch.vdot(u.ravel().to(torch.complex128), plan.apply_DFH(tr, x, v).ravel().to(torch.complex128))
+    assert abs(complex(lhs) - complex(rhs)) < 1e-5 * abs(complex(lhs))
+
+
+# ---------------------------------------------------------------------------
+# reconstruction
+# ---------------------------------------------------------------------------
+
+def _recon_compare(g, x_gpu, img_gpu, x_ref):
+    img_ref = O.image(g, x_ref)
+    e_img = rel(img_gpu, img_ref)
+    e_rc = rel(O.coil_images(g, x_gpu), O.coil_images(g, x_ref))
+    return e_img, e_rc
+
+
+def test_reconstruct_single_frame_c1(torch):
+    """Plain single frame: 64 px, 128 grid, 8 coils, 13 spokes x 128, 7 x 10."""
+    print_case("recon c1", N=64, J=8, K=13, M=7, C=10)
+    s = synth.single_frame(seed=1)
+    plan = nl().Plan(64, 8, 13, newton=7, cg=10)
+    z = plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0])
+    x, img, _ = plan.reconstruct(z, [0], want_img=True)
+    g = O.Geometry.make(64, 8)
+    P = O.psf_kernel(s.traj[0], g.R, g.G)
+    xr = O.reconstruct(g, O.grid(s.y[0], s.traj[0], g.R), P, newton=7, cg_iters=10)
+    e_img, e_rc = _recon_compare(g, host(x)[0], host(img)[0], xr)
+    print(f"c1 image rel {e_img:.2e}  rho*c rel {e_rc:.2e}")
+    assert e_img < IMG_TOL and e_rc < IMG_TOL
+
+
+def test_reconstruct_batched_series_with_prev(torch):
+    """Batch of 3 frames from 3 turns, each regularised to (and started from) a
+    different previous estimate; ragged sizes (J=5, K=7) on a 64-px grid."""
+    N, J, K, U, M, C = 32, 5, 7, 3, 4, 8
+    print_case("recon batched", N=N, J=J, K=K, U=U, M=M, C=C)
+    ser = synth.real_time_series(seed=5, N=N, J=J, J_phys=8, K=K, U=U, frames=4)
+    g = O.Geometry.make(N, J)
+    plan = nl().Plan(N, J, K, U=U, batch=3, newton=M, cg=C)
+    frames = [1, 2, 3]
+    # previous estimates: oracle results of frames 0..2 started from scratch
+    prevs = []
+    for f in [0, 1, 2]:
+        P = O.psf_kernel(ser.traj[f], g.R, g.G)
+        prevs.append(O.reconstruct(g, O.grid(ser.y[f], ser.traj[f], g.R), P, newton=2, cg_iters=4))
+    prevs = np.stack(prevs).astype(np.complex64)
+    turns = [int(ser.turn[f]) for f in frames]
+    z = plan.grid(dev(torch, ser.traj[frames]), dev(torch, ser.y[frames]), turns=turns)
+    xp = dev(torch, prevs)
+    x, img, _ = plan.reconstruct(z, turns, xprev=xp, init=2, want_img=True)
+    x, img = host(x), host(img)
+    for b, f in enumerate(frames):
+        P = O.psf_kernel(ser.traj[f], g.R, g.G)
+        xr = O.reconstruct(g, O.grid(ser.y[f], ser.traj[f], g.R), P, xprev=prevs[b], x0=prevs[b],
+                           newton=M, cg_iters=C)
+        e_img, e_rc = _recon_compare(g, x[b], img[b], xr)
+        print(f"batched item {b}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}")
+        assert e_img < IMG_TOL and e_rc < IMG_TOL
+
+
+def test_reconstruct_is_deterministic(torch):
+    s = synth.single_frame(seed=4, N=64, J=6, K=9)
+    plan = nl().Plan(64, 6, 9, newton=3, cg=6)
+    z = plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0])
+    x1, _, _ = plan.reconstruct(z, [0])
+    x2, _, _ = plan.reconstruct(z, [0])
+    assert torch.equal(x1, x2)
+
+
+def test_zero_data_is_a_fixed_point(torch):
+    plan = nl().Plan(32, 3, 5, newton=3, cg=4)
+    plan.psf(dev(torch, synth.radial_trajectory(32, 5, 64, 0, 1)), 0)
+    z = torch.zeros(1, 3, 32, 32, dtype=torch.complex64, device="cuda")
+    x, _, _ = plan.reconstruct(z, [0], init=1)
+    g = O.Geometry.make(32, 3)
+    assert np.array_equal(host(x)[0], g.initial().astype(np.complex64))
+
+
+def test_state_and_argument_errors(torch):
+    N = nl()
+    plan = N.Plan(32, 3, 5, U=2)
+    z = torch.zeros(1, 3, 32, 32, dtype=torch.complex64, device="cuda")
+    with pytest.raises(N.NlinvError) as ei:
+        plan.reconstruct(z, [1], init=1)          # PSF of turn 1 never computed
+    assert ei.value.code == N.E_STATE
+    with pytest.raises(N.NlinvError) as ei:
+        plan.reconstruct(z, [2], init=1)          # turn out of range
+    assert ei.value.code == N.E_ARG
+    x = torch.zeros(1, plan.X, dtype=torch.complex64, device="cuda")
+    plan.psf(dev(torch, synth.radial_trajectory(32, 5, 64, 0, 2)), 0)
+    with pytest.raises(N.NlinvError) as ei:
+        plan.reconstruct(z, [0], xprev=x, xhat=x, init=2)   # aliasing
+    assert ei.value.code == N.E_ARG
+
+
+# ---------------------------------------------------------------------------
+# full-size real-time series (160 px, 10 virtual coils, 15 spokes x 320, 7 x 20)
+# ---------------------------------------------------------------------------
+
+def test_real_time_series_first_frames_c2(torch):
+    print_case("recon c2 frames 0-1", N=160, J=10, K=15, M=7, C=20)
+    ser = synth.real_time_series(seed=2, frames=2)
+    g = O.Geometry.make(160, 10)
+    plan = nl().Plan(160, 10, 15, U=5, newton=7, cg=20)
+    x_prev_gpu = None
+    x_prev_ref = None
+    for f in range(2):
+        t = int(ser.turn[f])
+        z = plan.grid(dev(torch, ser.traj[f:f + 1]), dev(torch, ser.y[f:f + 1]), turns=[t])
+        x, img, _ = plan.reconstruct(z, [t], xprev=x_prev_gpu, want_img=True)
+        P = O.psf_kernel(ser.traj[f], g.R, g.G)
+        zr = O.grid(ser.y[f], ser.traj[f], g.R)
+        xr = O.reconstruct(g, zr, P, xprev=x_prev_ref, x0=x_prev_ref, newton=7, cg_iters=20)
+        e_img, e_rc = _recon_compare(g, host(x)[0], host(img)[0], xr)
+        print(f"c2 frame {f}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}", flush=True)
+        assert e_img < IMG_TOL and e_rc < IMG_TOL
+        x_prev_gpu = x.clone()
+        x_prev_ref = xr

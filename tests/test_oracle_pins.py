@@ -73,16 +73,19 @@ def test_nudft_matches_dense_matrix():
 
 
 def test_nudft_on_cartesian_grid_is_the_fft():
-    """With samples on the Cartesian grid k = m/R the NUDFT is numpy's unnormalised,
-    centred 2D FFT: pins the sign (exp(-i 2 pi k.r)), the x/y order and centring."""
+    """With samples on the Cartesian grid k = m/R the NUDFT is numpy's unitary
+    ("ortho"), centred 2D FFT: pins the sign (exp(-i 2 pi k.r)), the x/y order,
+    the centring and the 1/R scale."""
     R = 8
     m = O.centred(R) / R
     KY, KX = np.meshgrid(m, m, indexing="ij")
     traj = np.stack([KX.ravel(), KY.ravel()], axis=1)
     rng = np.random.default_rng(4)
     u = crand(rng, R, R)
-    ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(u)))
+    ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(u), norm="ortho"))
     assert rel(O.nudft(u, traj).reshape(R, R), ref) < 1e-12
+    # unitary: the adjoint inverts it
+    assert rel(O.nudft_adjoint(O.nudft(u, traj), traj, R), u) < 1e-12
 
 
 # --------------------------------------------------------------------------
@@ -119,19 +122,19 @@ def test_psf_kernel_is_real_and_lag_R_matters():
 
 
 def test_cartesian_full_coverage_gives_scaled_identity():
-    """All R^2 FOV frequencies sampled once -> psf = R^2 delta -> T = R^2 I."""
+    """All R^2 FOV frequencies sampled once -> psf = delta -> T = I."""
     R = 8
     m = O.centred(R) / R
     KY, KX = np.meshgrid(m, m, indexing="ij")
     traj = np.stack([KX.ravel(), KY.ravel()], axis=1)
     lag = O.psf_lags(traj, R)
     expect = np.zeros_like(lag)
-    expect[R - 1, R - 1] = R * R
+    expect[R - 1, R - 1] = 1.0
     assert np.max(np.abs(lag - expect)) < 1e-10
     P = O.psf_kernel(traj, R, 2 * R)
     rng = np.random.default_rng(6)
     u = crand(rng, R, R)
-    assert rel(O.toeplitz(u, P), R * R * u) < 1e-12
+    assert rel(O.toeplitz(u, P), u) < 1e-12
 
 
 def test_gridding_is_adjoint_nudft():
