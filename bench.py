@@ -62,10 +62,12 @@ def kernel_bytes(kind: str, B: int, fast: bool, turns_distinct: int) -> float:
     raise ValueError(kind)
 
 
-def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel):
-    """Advance B series by warmup + steps frames; returns per-step ms, total ms,
-    and the timer reading for `timer_kernel` over the timed steps."""
+def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, graphs):
+    """Advance B series by warmup + steps frames (timed), then kt_frames more
+    with HIP events around every launch of `timer_kernel`.  Returns per-step ms,
+    total ms of the timed steps, and the kernel timer reading (ms, launches)."""
     plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=(1 if fast else 0))
+    plan.set_graphs(graphs)
     import numpy as np
     traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()  # [F,B,K,S_r,2]
     y = torch.from_numpy(np.stack([d[1] for d in data], axis=1)).cuda()     # [F,B,J,S]
@@ -92,8 +94,6 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel):
         frame(n, xprev, bufs[n & 1])
         xprev = bufs[n & 1]
     torch.cuda.synchronize()
-    if timer_kernel:
-        plan.timer_enable(timer_kernel)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -106,7 +106,16 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel):
     torch.cuda.synchronize()
     total_ms = (time.perf_counter() - t0) * 1e3
     per = [a.elapsed_time(b) for a, b in ev]
-    kt = plan.timer_read() if timer_kernel else (0.0, 0)
+    kt = (0.0, 0)
+    if timer_kernel and kt_frames > 0:
+        # per-kernel HIP events need uncaptured launches; same kernels, same sizes
+        plan.timer_enable(timer_kernel)
+        for i in range(kt_frames):
+            n = warmup + steps + i
+            frame(n, xprev, bufs[n & 1])
+            xprev = bufs[n & 1]
+        kt = plan.timer_read()
+        plan.timer_enable("none")
     plan.close()
     return per, total_ms, kt
 
@@ -143,13 +152,18 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed frames per series (plain)")
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed frames; >= 10 so every (turn, buffer) graph is captured before timing")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--mode", choices=["both", "plain", "batched"], default="both")
     ap.add_argument("--fast", action="store_true", help="float32 half-transformed grid (NLINV_F_FAST)")
     ap.add_argument("--kernel", default="toeplitz_rows", help="kernel class timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true", help="launch kernels one by one (no HIP graphs)")
+    ap.add_argument("--kt-frames", type=int, default=3, help="frames with per-kernel event timing")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (reference kernel for HBM byte counters)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
 
@@ -158,8 +172,8 @@ def main():
                                    "(sharding across GPUs is described in DESIGN.md, not built)"}))
         sys.exit(2)
 
-    frames_plain = min(100, args.warmup + args.steps)
-    frames_batch = args.warmup + args.batch_steps
+    frames_plain = min(100, args.warmup + args.steps + args.kt_frames)
+    frames_batch = args.warmup + args.batch_steps + args.kt_frames
     t_gen = time.perf_counter()
     plain_data = make_data([2], frames_plain, 1) if args.mode != "batched" else None
     batch_data = (make_data(list(range(2, 2 + args.batch)), frames_batch, args.workers)
@@ -176,12 +190,22 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     nl.load()
 
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     kbytes, kms, klaunch = 0.0, 0.0, 0
     out = {"metric": "frames/sec + p99 frame latency, 160px 10ch NLINV, batched vs plain, 1 GPU",
            "unit": "frames/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
     if plain_data is not None:
-        per, total, (tms, tl) = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, args.fast, args.kernel)
+        per, total, (tms, tl) = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, args.fast, args.kernel,
+                                         args.kt_frames, not args.no_graphs)
         fps = args.steps / (total / 1e3)
         out.update({"value": fps, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps,
                     "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}})
@@ -191,7 +215,7 @@ def main():
     if batch_data is not None:
         B = args.batch
         per, total, (tms, tl) = run_mode(torch, nl, batch_data, B, args.batch_steps, args.warmup, args.fast,
-                                         args.kernel)
+                                         args.kernel, args.kt_frames, not args.no_graphs)
         out["batched"] = {"batch": B, "steps": args.batch_steps, "fps": B * args.batch_steps / (total / 1e3),
                           "ms_per_step": total / args.batch_steps,
                           "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}}
@@ -204,6 +228,7 @@ def main():
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
                      "plain_batch": 1, "batched_batch": args.batch, "fast_grid": bool(args.fast),
+                     "hip_graphs": not args.no_graphs,
                      "data_gen_s": round(t_gen, 1)}
     if klaunch:
         achieved = kbytes / (kms / 1e3) / 1e9

@@ -167,6 +167,14 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
  * |rho| sqrt(sum_j |c_j|^2) [B][R][R] of d_xhat; either output may be NULL. */
 int nlinv_coils(nlinv_plan plan, const nlinv_c64* d_xhat, nlinv_c64* d_coils, float* d_img);
 
+/* HIP graphs for nlinv_reconstruct (default off).  When enabled, the launch
+ * sequence of a reconstruction is captured once per distinct argument set
+ * (pointers, turns, init, outputs; up to 64 cached, then the cache is
+ * cleared) on an internal stream and replayed on the plan's stream, which
+ * removes the per-kernel host launch cost.  Results are identical to the
+ * uncaptured path.  Ignored while the kernel timer is enabled. */
+int nlinv_set_graphs(nlinv_plan plan, int32_t enable);
+
 /* Block until all work enqueued on the plan's stream has finished. */
 int nlinv_sync(nlinv_plan plan);
 

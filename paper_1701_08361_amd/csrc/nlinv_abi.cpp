@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,10 @@ struct nlinv_plan_s {
   int timer_kid = NLINV_KT_NONE;
   std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t ev_used = 0;
+  // HIP graphs of nlinv_reconstruct, one per distinct argument set
+  bool graphs = false;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graph_cache;
 };
 
 namespace {
@@ -59,7 +64,7 @@ bool supported_grid(int G) {
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -104,6 +109,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (S.NCH > st) st = S.NCH;
   S.stride = st;
   S.fast = (p->flags & NLINV_F_FAST) != 0;
+  S.gsplit = nlv::grid_nsplit(S.B, S.J, S.R);
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -123,6 +129,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->U2 = take(B * J * Gs * R * (S.fast ? c8 : c16));
   L->PR = take(B * J * R * R * c8);
   L->IMG = take(B * J * R * R * c8);
+  L->GS = take(S.gsplit > 1 ? (size_t)S.gsplit * B * J * R * R * c8 : 0);
   L->H = take(B * X * c16);
   L->Rv = take(B * X * c16);
   L->Pv0 = take(B * X * c16);
@@ -286,6 +293,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.U2 = static_cast<void*>(base + L.U2);
   w.PR = reinterpret_cast<float2*>(base + L.PR);
   w.IMG = reinterpret_cast<float2*>(base + L.IMG);
+  w.GS = reinterpret_cast<float2*>(base + L.GS);
   w.H = reinterpret_cast<double2*>(base + L.H);
   w.Rv = reinterpret_cast<double2*>(base + L.Rv);
   w.Pv[0] = reinterpret_cast<double2*>(base + L.Pv0);
@@ -325,6 +333,8 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
 int nlinv_plan_destroy(nlinv_plan plan) {
   if (!plan) return fail(nullptr, NLINV_E_ARG, "plan is NULL");
   for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+  for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   delete plan;
   return NLINV_OK;
 }
@@ -362,34 +372,18 @@ int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const
     }
   }
   NLV_HIP(plan, timed(plan, NLINV_KT_GRID, [&] {
-            return nlv::launch_grid(s, plan->stream, d_traj, reinterpret_cast<const float2*>(d_y),
+            return nlv::launch_grid(s, plan->w, plan->stream, d_traj, reinterpret_cast<const float2*>(d_y),
                                     reinterpret_cast<float2*>(d_z));
           }));
   return NLINV_OK;
 }
 
-int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_turn,
-                      const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init, float* d_img,
-                      nlinv_c64* d_coils) {
-  NLV_CHECK(check_plan(plan));
-  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
-  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
-  NLV_CHECK(check_ptr(plan, d_xprev, "d_xprev", true));
-  NLV_CHECK(check_ptr(plan, d_img, "d_img", true));
-  NLV_CHECK(check_ptr(plan, d_coils, "d_coils", true));
-  if (init < 0 || init > 2) return fail(plan, NLINV_E_ARG, "init must be 0, 1 or 2");
-  if (init == 2 && !d_xprev) return fail(plan, NLINV_E_ARG, "init = 2 needs d_xprev");
-  if (d_xprev && (const void*)d_xprev == (const void*)d_xhat)
-    return fail(plan, NLINV_E_ARG, "d_xhat must not alias d_xprev");
-  nlv::TurnArgs turns;
-  NLV_CHECK(turns_of(plan, h_turn, &turns));
-
+// Enqueue the whole reconstruction on plan->stream (validated arguments).
+static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
+                               const float2* xp, float2* xh, int init, float* d_img, float2* d_coils) {
   const Shape& s = plan->s;
   Bufs& w = plan->w;
   hipStream_t st = plan->stream;
-  float2* xh = reinterpret_cast<float2*>(d_xhat);
-  const float2* xp = reinterpret_cast<const float2*>(d_xprev);
-  const float2* z = reinterpret_cast<const float2*>(d_z);
   const Partials none{};
 
   if (init == 1) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, nullptr, 1));
@@ -420,11 +414,11 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
       const bool upd = i > 0;
       NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
                 return plan->t->coil_rows_cg(s, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
-                                                upd ? pc : nullptr, sc);
+                                             upd ? pc : nullptr, sc);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
                 return plan->t->cols_fwd(s, w, st, 1, w.CO, xh, upd ? pp : pc, upd ? w.Rv : nullptr,
-                                            upd ? pc : nullptr, sc, w.U2);
+                                         upd ? pc : nullptr, sc, w.U2);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
       NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
@@ -443,11 +437,74 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
   }
 
   if (d_img || d_coils) {
-    float2* co = d_coils ? reinterpret_cast<float2*>(d_coils) : w.CO;
+    float2* co = d_coils ? d_coils : w.CO;
     NLV_CHECK(coils_into(plan, xh, co));
     if (d_img) NLV_HIP(plan, nlv::launch_image(s, st, xh, co, d_img));
   }
   return NLINV_OK;
+}
+
+// Capture the reconstruction for this argument set once and replay it.
+static int graph_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
+                             const float2* xp, float2* xh, int init, float* d_img, float2* d_coils) {
+  std::vector<uintptr_t> key = {(uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)init,
+                                (uintptr_t)d_img, (uintptr_t)d_coils};
+  for (int b = 0; b < plan->s.B; ++b) key.push_back((uintptr_t)turns.t[b]);
+  auto it = plan->graph_cache.find(key);
+  if (it == plan->graph_cache.end()) {
+    if (plan->graph_cache.size() >= 64) {
+      for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
+      plan->graph_cache.clear();
+    }
+    if (!plan->cap_stream) NLV_HIP(plan, hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = plan->stream;
+    plan->stream = plan->cap_stream;
+    hipError_t e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      plan->stream = user;
+      return fail_hip(plan, e, "hipStreamBeginCapture");
+    }
+    const int rc = enqueue_reconstruct(plan, turns, z, xp, xh, init, d_img, d_coils);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(plan->cap_stream, &graph);
+    plan->stream = user;
+    if (rc != NLINV_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail_hip(plan, e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(plan, e, "hipGraphInstantiate");
+    it = plan->graph_cache.emplace(key, exec).first;
+  }
+  NLV_HIP(plan, hipGraphLaunch(it->second, plan->stream));
+  return NLINV_OK;
+}
+
+int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_turn,
+                      const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init, float* d_img,
+                      nlinv_c64* d_coils) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_xprev, "d_xprev", true));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img", true));
+  NLV_CHECK(check_ptr(plan, d_coils, "d_coils", true));
+  if (init < 0 || init > 2) return fail(plan, NLINV_E_ARG, "init must be 0, 1 or 2");
+  if (init == 2 && !d_xprev) return fail(plan, NLINV_E_ARG, "init = 2 needs d_xprev");
+  if (d_xprev && (const void*)d_xprev == (const void*)d_xhat)
+    return fail(plan, NLINV_E_ARG, "d_xhat must not alias d_xprev");
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+  const float2* z = reinterpret_cast<const float2*>(d_z);
+  const float2* xp = reinterpret_cast<const float2*>(d_xprev);
+  float2* xh = reinterpret_cast<float2*>(d_xhat);
+  float2* co = reinterpret_cast<float2*>(d_coils);
+  if (plan->graphs && plan->timer_kid == NLINV_KT_NONE)
+    return graph_reconstruct(plan, turns, z, xp, xh, init, d_img, co);
+  return enqueue_reconstruct(plan, turns, z, xp, xh, init, d_img, co);
 }
 
 int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat, nlinv_c64* d_y) {
@@ -497,7 +554,7 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
   const float2* xh = reinterpret_cast<const float2*>(d_xhat);
   float2* dx = reinterpret_cast<float2*>(d_dx);
   NLV_CHECK(coils_into(plan, xh, w.CO));
-  NLV_HIP(plan, nlv::launch_grid(s, plan->stream, d_traj, reinterpret_cast<const float2*>(d_dy), w.IMG));
+  NLV_HIP(plan, nlv::launch_grid(s, w, plan->stream, d_traj, reinterpret_cast<const float2*>(d_dy), w.IMG));
   NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, w.IMG, w.CO, xh, nullptr, nullptr, 0.0));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, xh, nullptr, 0.0, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, dx));
@@ -554,6 +611,12 @@ int nlinv_sync(nlinv_plan plan) {
 
 const char* nlinv_last_error(nlinv_plan plan) {
   return plan ? plan->err.c_str() : g_err.c_str();
+}
+
+int nlinv_set_graphs(nlinv_plan plan, int32_t enable) {
+  NLV_CHECK(check_plan(plan));
+  plan->graphs = enable != 0;
+  return NLINV_OK;
 }
 
 int nlinv_timer_enable(nlinv_plan plan, int32_t kernel_id) {

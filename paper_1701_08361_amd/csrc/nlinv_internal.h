@@ -9,7 +9,7 @@ namespace nlv {
 
 constexpr int ROWS = 8;       // lines per block in the row (x) passes
 constexpr int TW = 8;         // columns per block in the column (y) passes (8 x 16 B = 128 B)
-constexpr int CHUNK = 2048;   // vector elements per block in the CG kernels
+constexpr int CHUNK = 512;    // vector elements per block in the CG kernels
 constexpr int VT = 256;       // threads per block in the vector / NUDFT kernels
 constexpr int MAXB = 64;      // largest batch (turn table passed by value)
 
@@ -33,7 +33,12 @@ struct Shape {
   int NCH;             // vector chunks (ceil(X / CHUNK))
   int stride;          // partial slots per item
   bool fast;           // U2 stored in float32 instead of float64
+  int gsplit;          // sample-range split of the gridding kernel (1 = none)
 };
+
+// Gridding work decomposition (channels per block; sample-range split).
+int grid_jg(int J);
+int grid_nsplit(int B, int J, int R);
 
 // Device buffers carved from the caller's workspace.
 struct Bufs {
@@ -46,6 +51,7 @@ struct Bufs {
   void* U2;       // [B][J][G][R] half-transformed grid, double2 (or float2 when fast)
   float2* PR;     // [B][J][R][R] per-channel conj(c_j) t_j
   float2* IMG;    // [B][J][R][R] image-space scratch
+  float2* GS;     // [gsplit][B][J][R][R] partial gridding sums (gsplit > 1 only)
   double2* H;     // [B][X] CG iterate increment h
   double2* Rv;    // [B][X] CG residual r
   double2* Pv[2]; // [B][X] CG directions p (ping-pong)
@@ -98,7 +104,8 @@ hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const 
 hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const float2* src);
 hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);
 hipError_t launch_image(const Shape& s, hipStream_t st, const float2* xh, const float2* co, float* img);
-hipError_t launch_grid(const Shape& s, hipStream_t st, const float* traj, const float2* y, float2* z);
+hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, const float2* y,
+                       float2* z);
 hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
                             float2* y);
 hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int turn);

@@ -34,6 +34,12 @@ namespace nlv {
 
 using C = double2;   // arithmetic type of every transform
 
+// Blocks are padded to whole wavefronts; padding threads take part in barriers
+// and reductions only (their team lane is set past the last real lane).
+constexpr int pad64(int n) { return (n + 63) / 64 * 64; }
+template <int G> constexpr int rows_threads() { return pad64(ROWS * Team<G>::SIZE); }
+template <int G> constexpr int cols_threads() { return pad64(TW * Team<G>::SIZE); }
+
 // ---------------------------------------------------------------------------
 // reductions (FP64, fixed order, valid for blocks that are not whole waves)
 // ---------------------------------------------------------------------------
@@ -65,10 +71,31 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ p, 
   return block_sum<NT>(s, sh);
 }
 
+// Same for blocks made of whole wavefronts (NT a multiple of 64): shuffle within
+// each wave, then every thread adds the per-wave sums in the same order.
+template <int NT>
+__device__ __forceinline__ double block_sum_waves(double v, double* sh) {
+  static_assert(NT % 64 == 0, "whole wavefronts only");
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum_array_waves(const double* __restrict__ p, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+  return block_sum_waves<NT>(s, sh);
+}
+
 template <int NT>
 __device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh) {
-  const double rc = block_sum_array<NT>(sc.cur + (size_t)b * sc.stride, sc.ncur, sh);
-  const double rp = block_sum_array<NT>(sc.prev + (size_t)b * sc.stride, sc.nprev, sh);
+  const double rc = block_sum_array_waves<NT>(sc.cur + (size_t)b * sc.stride, sc.ncur, sh);
+  const double rp = block_sum_array_waves<NT>(sc.prev + (size_t)b * sc.stride, sc.nprev, sh);
   return rp != 0.0 ? rc / rp : 0.0;
 }
 
@@ -77,15 +104,16 @@ __device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh)
 // spectrum row i -> R image columns.  Optional fused p = r + beta p_old.
 // ---------------------------------------------------------------------------
 template <int G, class V>
-__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+__global__ void __launch_bounds__(rows_threads<G>())
 k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
             Partials sc, const float* __restrict__ dinv, const double2* __restrict__ tw,
             double2* __restrict__ U1, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NTH = ROWS * T::SIZE;
+  constexpr int R = G / 2, GC = G / 4, NTH = rows_threads<G>();
   __shared__ C lds[ROWS * T::LDSN];
   __shared__ double sh[NTH];
-  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
   const int row = blockIdx.x * ROWS + rl;
   const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
   const bool upd = rsrc != nullptr;
@@ -120,17 +148,18 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
 // MODE 1: u = c_j d_rho + rho d_c_j -> out (U2);  MODE 2 / 3: as 0 / 1 but u -> out (image, float32)
 // ---------------------------------------------------------------------------
 template <int G, int MODE, class S2>
-__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+__global__ void __launch_bounds__(cols_threads<G>())
 k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2* __restrict__ xh,
            const double2* __restrict__ psrc, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
            Partials sc, const double2* __restrict__ tw, void* __restrict__ outp, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = TW * T::SIZE;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
   constexpr bool NORMAL = (MODE == 1 || MODE == 3);
   constexpr bool TO_IMG = (MODE == 2 || MODE == 3);
   __shared__ C lds[TW * T::LDSN];
   __shared__ double sh[NTH];
-  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const bool act = (int)threadIdx.x < TW * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
   const int x = tile * TW + col;
   C* L = lds + col * T::LDSN;
@@ -184,18 +213,27 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 // toep_rows: along x, FFT (R inputs) -> x P(ky, kx) -> iFFT (R outputs), in place.
 // ---------------------------------------------------------------------------
 template <int G, class S2>
-__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+__global__ void __launch_bounds__(rows_threads<G>())
 k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
             const double2* __restrict__ tw, int J) {
   using T = Team<G>;
   constexpr int R = G / 2;
   __shared__ C lds[ROWS * T::LDSN];
-  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
   const int row = blockIdx.x * ROWS + rl;
   const int ky = row % G, b = row / G / J;
   S2* line = U2 + (size_t)row * R;
   const float* prow = P + ((size_t)turns.t[b] * G + ky) * G;
   C* L = lds + rl * T::LDSN;
+  // PSF kernel values of this thread's spectrum outputs, fetched before the transform
+  float pk[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      pk[k1] = prow[T::G2 * k1 + tl];
+    });
+  }
   C v[T::G1];
   fsA<G, -1>(tl, L, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
@@ -204,7 +242,7 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
-      v[k1] = cscale(v[k1], (double)prow[T::G2 * k1 + tl]);
+      v[k1] = cscale(v[k1], (double)pk[k1]);
     });
   }
   fsB<G, +1>(tl, L, tw, v, [&](int n, C val) {
@@ -218,16 +256,17 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
 // to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32).
 // ---------------------------------------------------------------------------
 template <int G, int MODE, class S2>
-__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+__global__ void __launch_bounds__(cols_threads<G>())
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
             const float2* __restrict__ z, const double2* __restrict__ pv, double alpha,
             const double2* __restrict__ tw, float2* __restrict__ PR, double2* __restrict__ U4,
             double* __restrict__ part, int stride, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = TW * T::SIZE;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
   __shared__ C lds[TW * T::LDSN];
   __shared__ double sh[NTH];
-  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const bool act = (int)threadIdx.x < TW * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
   const int x = tile * TW + col;
   C* L = lds + col * T::LDSN;
@@ -277,7 +316,7 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
     if (i >= 0) o[(size_t)i * R] = val;
   });
   if constexpr (MODE == 0) {
-    const double s = block_sum<NTH>(dot, sh);
+    const double s = block_sum_waves<NTH>(dot, sh);
     if (threadIdx.x == 0) part[(size_t)b * stride + j * NT + tile] = s;
   }
 }
@@ -289,16 +328,17 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
 // MODE 2: raw W^-H(.) -> out
 // ---------------------------------------------------------------------------
 template <int G, int MODE>
-__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+__global__ void __launch_bounds__(rows_threads<G>())
 k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
              const double2* __restrict__ pv, const float2* __restrict__ xh, const float2* __restrict__ xprev,
              double alpha, double2* __restrict__ out, double2* __restrict__ out2,
              double* __restrict__ part, int stride, int slot_off, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NTH = ROWS * T::SIZE;
+  constexpr int R = G / 2, GC = G / 4, NTH = rows_threads<G>();
   __shared__ C lds[ROWS * T::LDSN];
   __shared__ double sh[NTH];
-  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
   const int row = blockIdx.x * ROWS + rl;
   const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
   const double2* line = U4 + (size_t)row * R;
@@ -337,7 +377,7 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
     });
   }
   if constexpr (MODE != 2) {
-    const double s = block_sum<NTH>(acc, sh);
+    const double s = block_sum_waves<NTH>(acc, sh);
     const int blocal = blockIdx.x - b * (J * GC / ROWS);
     if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + blocal] = s;
   }
@@ -349,11 +389,12 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
 
 // Full G-point FFT along the rows of a G x G array (in place), forward.
 template <int G>
-__global__ void __launch_bounds__(ROWS * Team<G>::SIZE)
+__global__ void __launch_bounds__(rows_threads<G>())
 k_fft_rows_full(double2* __restrict__ a, const double2* __restrict__ tw) {
   using T = Team<G>;
   __shared__ C lds[ROWS * T::LDSN];
-  const int tl = threadIdx.x % T::SIZE, rl = threadIdx.x / T::SIZE;
+  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
   const int row = blockIdx.x * ROWS + rl;
   double2* line = a + (size_t)row * G;
   C v[T::G1];
@@ -368,12 +409,13 @@ k_fft_rows_full(double2* __restrict__ a, const double2* __restrict__ tw) {
 
 // Full forward FFT along the columns; P[ky][kx] = Re(.) * scale (float32).
 template <int G>
-__global__ void __launch_bounds__(TW * Team<G>::SIZE)
+__global__ void __launch_bounds__(cols_threads<G>())
 k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const double2* __restrict__ tw,
                double scale) {
   using T = Team<G>;
   __shared__ C lds[TW * T::LDSN];
-  const int col = threadIdx.x % TW, tl = threadIdx.x / TW;
+  const bool act = (int)threadIdx.x < TW * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int x = blockIdx.x * TW + col;
   C v[T::G1];
   fsA<G, -1>(tl, lds + col * T::LDSN, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
@@ -391,8 +433,8 @@ k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const doubl
 
 template <int G>
 struct GLaunch {
-  static constexpr int TH_ROWS = ROWS * Team<G>::SIZE;
-  static constexpr int TH_COLS = TW * Team<G>::SIZE;
+  static constexpr int TH_ROWS = rows_threads<G>();
+  static constexpr int TH_COLS = cols_threads<G>();
 
   static hipError_t coil_rows(const Shape& s, const Bufs& w, hipStream_t st, const float2* src) {
     k_coil_rows<G, float2><<<s.B * s.J * s.GC / ROWS, TH_ROWS, 0, st>>>(src, nullptr, nullptr, Partials{},

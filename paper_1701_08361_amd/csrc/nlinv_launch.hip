@@ -56,62 +56,78 @@ k_cg_init(const float2* __restrict__ PR, const float2* __restrict__ xh, const fl
     P0[ve] = bv;
     acc += bv.x * bv.x + bv.y * bv.y;
   }
-  const double s = block_sum<VT>(acc, sh);
+  const double s = block_sum_waves<VT>(acc, sh);
   if (threadIdx.x == 0) rr0[(size_t)b * stride + slot_off + c] = s;
 }
 
 // CG step: a = rr / Re<p, q>; h += a p; r -= a q; rr' partials.  The image block
 // of q is formed here from the channel partials: q_rho = sum_j PR_j + alpha p_rho.
 // On the last iteration the Newton update x += h is applied instead of the r update.
+// All element loads are issued before the scalar reductions so that their
+// latencies overlap.
 __global__ void __launch_bounds__(VT)
 k_cg_update(const float2* __restrict__ PR, const double2* __restrict__ Q, const double2* __restrict__ P,
             double2* __restrict__ H, double2* __restrict__ Rv, float2* __restrict__ xh,
             Partials rr, const double* __restrict__ pq, int npq, double alpha,
             double* __restrict__ rr_next, int first, int last, int J, int RR, long long X, int nchunk) {
+  constexpr int EPT = CHUNK / VT;
   __shared__ double sh[VT];
   const int b = blockIdx.x / nchunk, c = blockIdx.x - b * nchunk;
-  const double pqs = block_sum_array<VT>(pq + (size_t)b * rr.stride, npq, sh);
-  const double rrs = block_sum_array<VT>(rr.cur + (size_t)b * rr.stride, rr.ncur, sh);
-  const double a = pqs != 0.0 ? rrs / pqs : 0.0;
   const long long e0 = (long long)c * CHUNK;
-  const long long e1 = e0 + CHUNK < X ? e0 + CHUNK : X;
-  double acc = 0.0;
-  for (long long e = e0 + threadIdx.x; e < e1; e += VT) {
+  double2 pv[EPT], hv[EPT], rv[EPT], qv[EPT];
+  float2 xv[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const long long e = e0 + k * VT + threadIdx.x;
+    pv[k] = hv[k] = rv[k] = qv[k] = make_double2(0.0, 0.0);
+    xv[k] = make_float2(0.f, 0.f);
+    if (e >= X) continue;
     const size_t ve = (size_t)b * X + e;
-    const double2 p = P[ve];
-    double hx = a * p.x, hy = a * p.y;
-    if (!first) {
-      const double2 h = H[ve];
-      hx += h.x;
-      hy += h.y;
-    }
+    pv[k] = P[ve];
+    if (!first) hv[k] = H[ve];
     if (last) {
-      const float2 x = xh[ve];
-      xh[ve] = make_float2((float)(x.x + hx), (float)(x.y + hy));
+      xv[k] = xh[ve];
     } else {
-      double qx, qy;
+      rv[k] = Rv[ve];
       if (e < RR) {
-        qx = alpha * p.x;
-        qy = alpha * p.y;
+        double qx = 0.0, qy = 0.0;
         for (int j = 0; j < J; ++j) {
           const float2 pr = PR[((size_t)b * J + j) * RR + e];
           qx += pr.x;
           qy += pr.y;
         }
+        qv[k] = make_double2(qx, qy);
       } else {
-        const double2 q = Q[ve];
-        qx = q.x;
-        qy = q.y;
+        qv[k] = Q[ve];
+      }
+    }
+  }
+  const double pqs = block_sum_array_waves<VT>(pq + (size_t)b * rr.stride, npq, sh);
+  const double rrs = block_sum_array_waves<VT>(rr.cur + (size_t)b * rr.stride, rr.ncur, sh);
+  const double a = pqs != 0.0 ? rrs / pqs : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const long long e = e0 + k * VT + threadIdx.x;
+    if (e >= X) continue;
+    const size_t ve = (size_t)b * X + e;
+    const double hx = hv[k].x + a * pv[k].x, hy = hv[k].y + a * pv[k].y;
+    if (last) {
+      xh[ve] = make_float2((float)(xv[k].x + hx), (float)(xv[k].y + hy));
+    } else {
+      double qx = qv[k].x, qy = qv[k].y;
+      if (e < RR) {
+        qx += alpha * pv[k].x;
+        qy += alpha * pv[k].y;
       }
       H[ve] = make_double2(hx, hy);
-      const double2 r = Rv[ve];
-      const double2 rn = make_double2(r.x - a * qx, r.y - a * qy);
+      const double2 rn = make_double2(rv[k].x - a * qx, rv[k].y - a * qy);
       Rv[ve] = rn;
       acc += rn.x * rn.x + rn.y * rn.y;
     }
   }
   if (!last) {
-    const double s = block_sum<VT>(acc, sh);
+    const double s = block_sum_waves<VT>(acc, sh);
     if (threadIdx.x == 0) rr_next[(size_t)b * rr.stride + c] = s;
   }
 }
@@ -206,64 +222,110 @@ __device__ __forceinline__ float2 cis_cycles(float k, int m) {
 constexpr int GSC = 64;   // samples per LDS stage
 constexpr int GT = 16;    // pixel tile side (16 x 16 = 256 threads)
 
-// z[b][j][y][x] = scale sum_s y[b][j][s] exp(+i 2 pi (kx_s x + ky_s y)), x, y in [-R/2, R/2)
+// Gridding, register-blocked: a block owns a 32 x 32 pixel tile and JG channels,
+// each thread a 2 x 2 pixel patch; samples are staged in LDS 32 at a time
+// (phase factors exp(+i 2 pi k x) and exp(+i 2 pi k y) per sample and tile row /
+// column), float32 sums per stage are accumulated in float64.  With nsplit > 1
+// the sample range is split over blocks and out receives nsplit partial grids
+// [nsplit][B][J][R][R] that k_grid_reduce adds in a fixed order.
+constexpr int GS2 = 32;
 template <int JG>
 __global__ void __launch_bounds__(VT)
-k_grid(const float* __restrict__ traj, const float2* __restrict__ yv, float2* __restrict__ z,
-       int J, int S, int R, float scale) {
-  __shared__ float2 ex[GSC][GT], ey[GSC][GT], ys[JG][GSC];
-  const int nt = R / GT;
-  const int ty0 = (blockIdx.x / nt) * GT, tx0 = (blockIdx.x % nt) * GT;
-  const int jg = blockIdx.y, b = blockIdx.z;
-  const int py = threadIdx.x / GT, px = threadIdx.x % GT;
+k_grid2(const float* __restrict__ traj, const float2* __restrict__ yv, float2* __restrict__ out,
+        int J, int S, int R, int B, int nsplit, float scale) {
+  __shared__ __align__(16) float2 ex[GS2][32];
+  __shared__ __align__(16) float2 ey[GS2][32];
+  __shared__ float2 ys[JG][GS2];
+  const int nt = R / 32;
+  const int ty0 = (blockIdx.x / nt) * 32, tx0 = (blockIdx.x % nt) * 32;
+  const int jg = blockIdx.y;
+  const int b = blockIdx.z / nsplit, sp = blockIdx.z - b * nsplit;
+  const int per = (S + nsplit - 1) / nsplit;
+  const int s_lo = sp * per, s_hi = min(S, s_lo + per);
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
   const float* tr = traj + (size_t)b * S * 2;
-  double2 acc[JG];   // float32 sums over GSC samples, accumulated in float64
+  double2 acc[JG][4];
 #pragma unroll
-  for (int q = 0; q < JG; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int s0 = 0; s0 < S; s0 += GSC) {
-    for (int q = threadIdx.x; q < GSC * GT; q += VT) {
-      const int ss = q / GT, pix = q % GT, s = s0 + ss;
-      if (s < S) {
-        const float kx = tr[2 * s], ky = tr[2 * s + 1];
-        ex[ss][pix] = cis_cycles<+1>(kx, tx0 + pix - R / 2);
-        ey[ss][pix] = cis_cycles<+1>(ky, ty0 + pix - R / 2);
+  for (int q = 0; q < JG; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[q][k] = make_double2(0.0, 0.0);
+  for (int s0 = s_lo; s0 < s_hi; s0 += GS2) {
+    for (int q = threadIdx.x; q < GS2 * 32; q += VT) {
+      const int ss = q / 32, pix = q % 32, s = s0 + ss;
+      if (s < s_hi) {
+        ex[ss][pix] = cis_cycles<+1>(tr[2 * s], tx0 + pix - R / 2);
+        ey[ss][pix] = cis_cycles<+1>(tr[2 * s + 1], ty0 + pix - R / 2);
       } else {
         ex[ss][pix] = czero<float2>();
         ey[ss][pix] = czero<float2>();
       }
     }
-    for (int q = threadIdx.x; q < JG * GSC; q += VT) {
-      const int jj = q / GSC, ss = q % GSC, s = s0 + ss, j = jg * JG + jj;
-      ys[jj][ss] = (s < S && j < J) ? yv[((size_t)b * J + j) * S + s] : czero<float2>();
+    for (int q = threadIdx.x; q < JG * GS2; q += VT) {
+      const int jj = q / GS2, ss = q % GS2, s = s0 + ss, j = jg * JG + jj;
+      ys[jj][ss] = (s < s_hi && j < J) ? yv[((size_t)b * J + j) * S + s] : czero<float2>();
     }
     __syncthreads();
-    float2 part[JG];
+    float2 part[JG][4];
 #pragma unroll
-    for (int q = 0; q < JG; ++q) part[q] = czero<float2>();
-#pragma unroll 4
-    for (int ss = 0; ss < GSC; ++ss) {
-      const float2 e = cmul(ey[ss][py], ex[ss][px]);
+    for (int q = 0; q < JG; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) part[q][k] = czero<float2>();
+#pragma unroll 2
+    for (int ss = 0; ss < GS2; ++ss) {
+      const float4 xx = *reinterpret_cast<const float4*>(&ex[ss][2 * tx]);
+      const float4 yy = *reinterpret_cast<const float4*>(&ey[ss][2 * ty]);
+      const float2 ex0 = make_float2(xx.x, xx.y), ex1 = make_float2(xx.z, xx.w);
+      const float2 ey0 = make_float2(yy.x, yy.y), ey1 = make_float2(yy.z, yy.w);
+      float2 e[4];
+      e[0] = cmul(ey0, ex0);
+      e[1] = cmul(ey0, ex1);
+      e[2] = cmul(ey1, ex0);
+      e[3] = cmul(ey1, ex1);
 #pragma unroll
       for (int q = 0; q < JG; ++q) {
         const float2 y = ys[q][ss];
-        part[q].x += y.x * e.x - y.y * e.y;
-        part[q].y += y.x * e.y + y.y * e.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          part[q][k].x += y.x * e[k].x - y.y * e[k].y;
+          part[q][k].y += y.x * e[k].y + y.y * e[k].x;
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < JG; ++q) {
-      acc[q].x += part[q].x;
-      acc[q].y += part[q].y;
-    }
+    for (int q = 0; q < JG; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc[q][k].x += part[q][k].x;
+        acc[q][k].y += part[q][k].y;
+      }
     __syncthreads();
   }
+  float2* o = out + (nsplit > 1 ? (size_t)sp * B * J * R * R : 0);
 #pragma unroll
   for (int q = 0; q < JG; ++q) {
     const int j = jg * JG + q;
-    if (j < J)
-      z[(((size_t)b * J + j) * R + ty0 + py) * R + tx0 + px] =
-          make_float2((float)(acc[q].x * scale), (float)(acc[q].y * scale));
+    if (j >= J) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int y = ty0 + 2 * ty + (k >> 1), x = tx0 + 2 * tx + (k & 1);
+      o[(((size_t)b * J + j) * R + y) * R + x] =
+          make_float2((float)(acc[q][k].x * scale), (float)(acc[q][k].y * scale));
+    }
   }
+}
+
+// z = sum over the nsplit partial grids (fixed order, float64 sum)
+__global__ void __launch_bounds__(VT)
+k_grid_reduce(const float2* __restrict__ part, float2* __restrict__ z, long long n, int nsplit) {
+  const long long e = (long long)blockIdx.x * VT + threadIdx.x;
+  if (e >= n) return;
+  double sx = 0.0, sy = 0.0;
+  for (int k = 0; k < nsplit; ++k) {
+    const float2 v = part[(size_t)k * n + e];
+    sx += v.x;
+    sy += v.y;
+  }
+  z[e] = make_float2((float)sx, (float)sy);
 }
 
 // psf[n_y][n_x] = sum_s exp(+i 2 pi k_s . d), d = n or n - G, kept for |d| <= R-1, else 0.
@@ -387,19 +449,39 @@ hipError_t launch_image(const Shape& s, hipStream_t st, const float2* xh, const 
   return hipGetLastError();
 }
 
-hipError_t launch_grid(const Shape& s, hipStream_t st, const float* traj, const float2* y, float2* z) {
-  const int nt = (s.R / GT) * (s.R / GT);
-  auto go = [&](auto jg) {
-    constexpr int JG = decltype(jg)::value;
-    dim3 grid(nt, (s.J + JG - 1) / JG, s.B);
-    k_grid<JG><<<grid, VT, 0, st>>>(traj, y, z, s.J, s.S, s.R, 1.0f / s.R);
-  };
-  if (s.J % 8 == 0) go(IC<8>{});
-  else if (s.J % 5 == 0) go(IC<5>{});
-  else if (s.J % 4 == 0) go(IC<4>{});
-  else if (s.J % 3 == 0) go(IC<3>{});
-  else if (s.J % 2 == 0) go(IC<2>{});
-  else go(IC<1>{});
+int grid_jg(int J) {
+  if (J % 5 == 0) return 5;
+  if (J % 4 == 0) return 4;
+  if (J % 3 == 0) return 3;
+  if (J % 2 == 0) return 2;
+  return J >= 4 ? 4 : 1;
+}
+
+int grid_nsplit(int B, int J, int R) {
+  const long long blocks = (long long)(R / 32) * (R / 32) * ((J + grid_jg(J) - 1) / grid_jg(J)) * B;
+  int n = 1;
+  while (n < 8 && blocks * n < 512) n *= 2;
+  return n;
+}
+
+hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, const float2* y,
+                       float2* z) {
+  const int JG = grid_jg(s.J);
+  const int nsplit = s.gsplit;
+  float2* out = nsplit > 1 ? w.GS : z;
+  dim3 grid((s.R / 32) * (s.R / 32), (s.J + JG - 1) / JG, s.B * nsplit);
+  const float scale = 1.0f / s.R;
+  switch (JG) {
+    case 5: k_grid2<5><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
+    case 4: k_grid2<4><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
+    case 3: k_grid2<3><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
+    case 2: k_grid2<2><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
+    default: k_grid2<1><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nsplit == 1) return e;
+  const long long n = (long long)s.B * s.J * s.R * s.R;
+  k_grid_reduce<<<(int)((n + VT - 1) / VT), VT, 0, st>>>(w.GS, z, n, nsplit);
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ def load() -> ctypes.CDLL:
         "nlinv_apply_normal": [_P, _P, _P, ctypes.c_double, _P, _P],
         "nlinv_coils": [_P, _P, _P, _P],
         "nlinv_sync": [_P],
+        "nlinv_set_graphs": [_P, _I],
         "nlinv_timer_enable": [_P, _I],
         "nlinv_timer_read": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     }
@@ -278,6 +279,9 @@ class Plan:
         self._stream_sync()
         _check(self.lib.nlinv_coils(self.handle, self._ptr(xhat), self._ptr(coils), self._ptr(img)), self.handle)
         return coils, img
+
+    def set_graphs(self, enable: bool = True):
+        _check(self.lib.nlinv_set_graphs(self.handle, 1 if enable else 0), self.handle)
 
     def timer_enable(self, kernel: str):
         _check(self.lib.nlinv_timer_enable(self.handle, KT[kernel]), self.handle)

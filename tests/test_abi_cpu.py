@@ -38,7 +38,8 @@ def test_sizes(lib, N, J, K, expect):
 def test_workspace_grows_with_batch(lib):
     a = nl.workspace_size(nl.make_params(160, 10, 15, batch=1))
     b = nl.workspace_size(nl.make_params(160, 10, 15, batch=16))
-    assert 10 * a < b < 17 * a
+    # batch-1 plans also hold the split-gridding partial sums
+    assert 4 * a < b < 17 * a
 
 
 @pytest.mark.parametrize("kw,code", [

@@ -218,6 +218,32 @@ def test_reconstruct_is_deterministic(torch):
     assert torch.equal(x1, x2)
 
 
+def test_graph_replays_match_eager(torch):
+    """Captured reconstructions (HIP graphs) replayed several times, with eager
+    work and synchronisations in between, equal the uncaptured path bit for bit."""
+    N, J, K, U = 64, 5, 9, 2
+    ser = synth.real_time_series(seed=9, N=N, J=J, J_phys=6, K=K, U=U, frames=2)
+    plan = nl().Plan(N, J, K, U=U, newton=3, cg=5)
+    z0 = plan.grid(dev(torch, ser.traj[0:1]), dev(torch, ser.y[0:1]), turns=[0])
+    z1 = plan.grid(dev(torch, ser.traj[1:2]), dev(torch, ser.y[1:2]), turns=[1])
+    x0, img0, _ = plan.reconstruct(z0, [0], init=1, want_img=True)
+    x1, img1, _ = plan.reconstruct(z1, [1], xprev=x0, init=2, want_img=True)
+    ref0, ref1, refi = x0.clone(), x1.clone(), img1.clone()
+    plan.set_graphs(True)
+    a = torch.empty_like(ref0)
+    bb = torch.empty_like(ref0)
+    img = torch.empty_like(refi)
+    for rep in range(3):
+        a.fill_(float(rep))
+        bb.zero_()
+        torch.cuda.synchronize()
+        plan.reconstruct(z0, [0], xhat=a, init=1)
+        plan.reconstruct(z1, [1], xprev=a, xhat=bb, init=2, img=img)
+        torch.cuda.synchronize()
+        assert torch.equal(a, ref0) and torch.equal(bb, ref1) and torch.equal(img, refi), f"replay {rep}"
+    plan.set_graphs(False)
+
+
 def test_zero_data_is_a_fixed_point(torch):
     plan = nl().Plan(32, 3, 5, newton=3, cg=4)
     plan.psf(dev(torch, synth.radial_trajectory(32, 5, 64, 0, 1)), 0)
@@ -248,22 +274,33 @@ def test_state_and_argument_errors(torch):
 # full-size real-time series (160 px, 10 virtual coils, 15 spokes x 320, 7 x 20)
 # ---------------------------------------------------------------------------
 
-def test_real_time_series_first_frames_c2(torch):
-    print_case("recon c2 frames 0-1", N=160, J=10, K=15, M=7, C=20)
+@pytest.fixture(scope="module")
+def c2_oracle():
+    """Oracle reconstructions of frames 0 and 1 of the 160 px series (frame 1
+    regularised to and started from frame 0)."""
     ser = synth.real_time_series(seed=2, frames=2)
     g = O.Geometry.make(160, 10)
-    plan = nl().Plan(160, 10, 15, U=5, newton=7, cg=20)
+    out, prev = [], None
+    for f in range(2):
+        P = O.psf_kernel(ser.traj[f], g.R, g.G)
+        zr = O.grid(ser.y[f], ser.traj[f], g.R)
+        prev = O.reconstruct(g, zr, P, xprev=prev, x0=prev, newton=7, cg_iters=20)
+        out.append(prev)
+    return ser, g, out
+
+
+@pytest.mark.parametrize("flags", [0, 1], ids=["default", "fast"])
+def test_real_time_series_first_frames_c2(torch, c2_oracle, flags):
+    """160 px, 10 virtual coils, 15 spokes x 320, 7 x 20, frames 0 and 1 (full size)."""
+    print_case("recon c2 frames 0-1", N=160, J=10, K=15, M=7, C=20, flags=flags)
+    ser, g, refs = c2_oracle
+    plan = nl().Plan(160, 10, 15, U=5, newton=7, cg=20, flags=flags)
     x_prev_gpu = None
-    x_prev_ref = None
     for f in range(2):
         t = int(ser.turn[f])
         z = plan.grid(dev(torch, ser.traj[f:f + 1]), dev(torch, ser.y[f:f + 1]), turns=[t])
         x, img, _ = plan.reconstruct(z, [t], xprev=x_prev_gpu, want_img=True)
-        P = O.psf_kernel(ser.traj[f], g.R, g.G)
-        zr = O.grid(ser.y[f], ser.traj[f], g.R)
-        xr = O.reconstruct(g, zr, P, xprev=x_prev_ref, x0=x_prev_ref, newton=7, cg_iters=20)
-        e_img, e_rc = _recon_compare(g, host(x)[0], host(img)[0], xr)
-        print(f"c2 frame {f}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}", flush=True)
+        e_img, e_rc = _recon_compare(g, host(x)[0], host(img)[0], refs[f])
+        print(f"c2 flags={flags} frame {f}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}", flush=True)
         assert e_img < IMG_TOL and e_rc < IMG_TOL
         x_prev_gpu = x.clone()
-        x_prev_ref = xr
