@@ -371,3 +371,63 @@ def coil_images(g: Geometry, x: np.ndarray) -> np.ndarray:
     """rho . c_j -> [J, R, R] (invariant under rho -> a rho, c -> c / a)."""
     rho, _ = g.unpack(x)
     return rho[None] * g.coils(x)
+
+
+# ---------------------------------------------------------------------------
+# frame series: strict order and relaxed temporal coupling (Sec. 4.2,
+# temporal decomposition, equation for h(n, m))
+# ---------------------------------------------------------------------------
+
+def relaxed_sources(F: int, l: int, o: int) -> list:
+    """Source frame s(n) of every frame n < F for the Newton steps m < M-1.
+
+    The equation for h(n, m) sends frame n to frame n-1 for n <= l, and for
+    n > l to the most recent finished frame in [n-o, n-1].  Reading of
+    "most recent finished": frames after l are taken in consecutive groups of
+    o frames, l+1 .. l+o, l+o+1 .. l+2o, ...; a group starts once the frame
+    before it has finished, so that frame is the most recent finished one
+    for every member of the group (it lies in [n-o, n-1]).  Frame 0 has no
+    source (-1: rho = 1, c = 0)."""
+    if F < 0 or l < 0 or o < 1:
+        raise ValueError("need F >= 0, l >= 0, o >= 1")
+    src = []
+    for n in range(F):
+        if n == 0:
+            src.append(-1)
+        elif n <= l:
+            src.append(n - 1)
+        else:
+            start = l + 1 + ((n - l - 1) // o) * o
+            src.append(start - 1)
+    return src
+
+
+def reconstruct_series(g: Geometry, zs, Ps, sources: list | None = None, newton: int = 7,
+                       cg_iters: int = 10, alpha0: float = 1.0, alpha_q: float = 0.5,
+                       alpha_min: float = 0.0) -> list:
+    """Reconstruct frames n = 0 .. F-1 of one series (zs[n]: gridded data,
+    Ps[n]: PSF kernel of the frame's turn).
+
+    Frame n starts from x_{h(n, 0)} and Newton step m is regularised towards
+    x_{h(n, m)}, where h(n, m) = n - 1 for the last step m = M-1 and
+    h(n, m) = sources[n] for m < M-1 (equation for h(n, m), Sec. 4.2).
+    sources = None is the strict order h(n, m) = n - 1.  Frame 0 starts from
+    and is regularised towards (rho = 1, c = 0) (Sec. 4.2)."""
+    F = len(zs)
+    if sources is None:
+        sources = [n - 1 for n in range(F)]
+    alphas = alpha_schedule(newton, alpha0, alpha_q, alpha_min)
+    out: list = []
+
+    def frame(k: int) -> np.ndarray:
+        return g.initial() if k < 0 else out[k]
+
+    for n in range(F):
+        h = [n - 1 if m == newton - 1 else sources[n] for m in range(newton)]
+        if n == 0:
+            h = [-1] * newton
+        x = frame(h[0]).copy()
+        for m, alpha in enumerate(alphas):
+            x = x + newton_step(g, x, frame(h[m]), zs[n], Ps[n], alpha, cg_iters)
+        out.append(x)
+    return out
