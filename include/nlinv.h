@@ -143,6 +143,34 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
                       const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init,
                       float* d_img, nlinv_c64* d_coils);
 
+/* Relaxed temporal coupling (Sec. 4.2, temporal decomposition, equation for
+ * h(n, m)): reconstruct `count` consecutive frames n0 .. n0+count-1 of one
+ * series (1 <= count <= batch) together.
+ *   d_z     [count][J][R][R]  gridded data of the frames, in order
+ *   h_turn  host [count]      PSF kernel of each frame's turn
+ *   d_xprev [X]               result of frame n0-1 (the source frame, the most
+ *                             recent finished one); NULL -> (rho = 1, c = 0)
+ *   d_xhat  [count][X]        out: results
+ *   d_img, d_coils            as nlinv_reconstruct ([count] items), or NULL
+ * Newton steps m < M-1 of every frame start from, and are regularised
+ * towards, d_xprev; they run as one batch.  Step M-1 of frame n0+k is
+ * regularised towards frame n0+k-1 (d_xprev for k = 0) and runs after it, one
+ * frame at a time; with M = 1 that step also starts from frame n0+k-1.
+ * count = 1 gives the strict per-frame order (nlinv_reconstruct with init =
+ * 2, or init = 1 when d_xprev is NULL).  d_xhat must not overlap d_xprev or
+ * d_z.  Uses the active-batch setting internally and restores it. */
+int nlinv_reconstruct_frames(nlinv_plan plan, int32_t count, const nlinv_c64* d_z,
+                             const int32_t* h_turn, const nlinv_c64* d_xprev,
+                             nlinv_c64* d_xhat, float* d_img, nlinv_c64* d_coils);
+
+/* Active batch: calls after nlinv_set_batch(plan, b) work on the first b
+ * items (1 <= b <= batch); every [B] in this header then means [b].  A plan
+ * starts with b = batch.  Lets one plan serve partial batches, e.g. frames
+ * that have arrived so far.  nlinv_get_batch returns the setting (0 for a
+ * NULL plan). */
+int nlinv_set_batch(nlinv_plan plan, int32_t b);
+int32_t nlinv_get_batch(nlinv_plan plan);
+
 /* Operators at the linearisation point d_xhat [B][X] (Sec. 2.2), mapping
  * between the unknowns and the radial measurement space [B][J][S]:
  *   F_hat(x)_j    = F(rho . W^-1 c_hat_j)

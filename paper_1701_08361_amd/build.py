@@ -21,6 +21,8 @@ ARCH = os.environ.get("NLINV_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # lets x + 0.0 fold, so constant-zero transform inputs are removed at compile time
+    "-fno-signed-zeros",
     # packed FP32 instructions stay off (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -21,7 +22,7 @@ using nlv::Shape;
 
 struct nlinv_plan_s {
   nlinv_params p;
-  Shape s;
+  Shape s;   // shape of the active batch (s.B <= p.batch)
   Bufs w;
   const nlv::GTable* t = nullptr;
   hipStream_t stream = nullptr;
@@ -34,6 +35,7 @@ struct nlinv_plan_s {
   bool graphs = false;
   hipStream_t cap_stream = nullptr;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graph_cache;
+  float2* xb = nullptr;   // [B][X] source frames of nlinv_reconstruct_frames
 };
 
 namespace {
@@ -64,7 +66,7 @@ bool supported_grid(int G) {
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -129,7 +131,13 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->U2 = take(B * J * Gs * R * (S.fast ? c8 : c16));
   L->PR = take(B * J * R * R * c8);
   L->IMG = take(B * J * R * R * c8);
-  L->GS = take(S.gsplit > 1 ? (size_t)S.gsplit * B * J * R * R * c8 : 0);
+  // partial gridding sums: enough for the split of every active batch size
+  size_t gs_items = 0;
+  for (int b = 1; b <= S.B; ++b) {
+    const int n = nlv::grid_nsplit(b, S.J, S.R);
+    if (n > 1) gs_items = std::max(gs_items, (size_t)n * b);
+  }
+  L->GS = take(gs_items * J * R * R * c8);
   L->H = take(B * X * c16);
   L->Rv = take(B * X * c16);
   L->Pv0 = take(B * X * c16);
@@ -138,6 +146,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->pq = take(B * (size_t)S.stride * 8);
   L->rr0 = take(B * (size_t)S.stride * 8);
   L->rr1 = take(B * (size_t)S.stride * 8);
+  L->XB = take(B * X * c8);
   L->total = off;
   return NLINV_OK;
 }
@@ -210,6 +219,19 @@ int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
           }));
   return NLINV_OK;
 }
+
+// Make the first b items of every array the active batch.
+void set_active(nlinv_plan plan, int b) {
+  plan->s.B = b;
+  plan->s.gsplit = nlv::grid_nsplit(b, plan->s.J, plan->s.R);
+}
+
+// Restores the active batch size on scope exit.
+struct ActiveGuard {
+  nlinv_plan plan;
+  int b;
+  ~ActiveGuard() { set_active(plan, b); }
+};
 
 }  // namespace
 
@@ -302,6 +324,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.pq = reinterpret_cast<double*>(base + L.pq);
   w.rr[0] = reinterpret_cast<double*>(base + L.rr0);
   w.rr[1] = reinterpret_cast<double*>(base + L.rr1);
+  plan->xb = reinterpret_cast<float2*>(base + L.XB);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -378,9 +401,11 @@ int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const
   return NLINV_OK;
 }
 
-// Enqueue the whole reconstruction on plan->stream (validated arguments).
+// Enqueue Newton steps m0 <= m < m1 of the reconstruction on plan->stream
+// (validated arguments); alpha_m follows the schedule from step 0.
 static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
-                               const float2* xp, float2* xh, int init, float* d_img, float2* d_coils) {
+                               const float2* xp, float2* xh, int init, int m0, int m1, float* d_img,
+                               float2* d_coils) {
   const Shape& s = plan->s;
   Bufs& w = plan->w;
   hipStream_t st = plan->stream;
@@ -390,7 +415,8 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   if (init == 2) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, xp, 2));
 
   double alpha = plan->p.alpha0;
-  for (int n = 0; n < plan->p.newton; ++n) {
+  for (int n = 0; n < m0; ++n) alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
+  for (int n = m0; n < m1; ++n) {
     // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
     NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, w, st, xh); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
@@ -444,12 +470,9 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   return NLINV_OK;
 }
 
-// Capture the reconstruction for this argument set once and replay it.
-static int graph_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
-                             const float2* xp, float2* xh, int init, float* d_img, float2* d_coils) {
-  std::vector<uintptr_t> key = {(uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)init,
-                                (uintptr_t)d_img, (uintptr_t)d_coils};
-  for (int b = 0; b < plan->s.B; ++b) key.push_back((uintptr_t)turns.t[b]);
+// Capture the launch sequence enqueued by `body` once per key and replay it.
+static int run_captured(nlinv_plan plan, std::vector<uintptr_t> key, const std::function<int()>& body) {
+  key.push_back((uintptr_t)plan->s.B);
   auto it = plan->graph_cache.find(key);
   if (it == plan->graph_cache.end()) {
     if (plan->graph_cache.size() >= 64) {
@@ -464,7 +487,7 @@ static int graph_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const 
       plan->stream = user;
       return fail_hip(plan, e, "hipStreamBeginCapture");
     }
-    const int rc = enqueue_reconstruct(plan, turns, z, xp, xh, init, d_img, d_coils);
+    const int rc = body();
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(plan->cap_stream, &graph);
     plan->stream = user;
@@ -502,10 +525,96 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
   const float2* xp = reinterpret_cast<const float2*>(d_xprev);
   float2* xh = reinterpret_cast<float2*>(d_xhat);
   float2* co = reinterpret_cast<float2*>(d_coils);
-  if (plan->graphs && plan->timer_kid == NLINV_KT_NONE)
-    return graph_reconstruct(plan, turns, z, xp, xh, init, d_img, co);
-  return enqueue_reconstruct(plan, turns, z, xp, xh, init, d_img, co);
+  const int M = plan->p.newton;
+  auto body = [&] { return enqueue_reconstruct(plan, turns, z, xp, xh, init, 0, M, d_img, co); };
+  if (plan->graphs && plan->timer_kid == NLINV_KT_NONE) {
+    std::vector<uintptr_t> key = {0, (uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)init,
+                                  (uintptr_t)d_img, (uintptr_t)co};
+    for (int b = 0; b < plan->s.B; ++b) key.push_back((uintptr_t)turns.t[b]);
+    return run_captured(plan, std::move(key), body);
+  }
+  return body();
 }
+
+// Frames n0 .. n0+count-1 of one series under the relaxed temporal coupling.
+static int enqueue_frames(nlinv_plan plan, int count, const nlv::TurnArgs& turns, const float2* z,
+                          const float2* xp, float2* xh, float* d_img, float2* d_coils) {
+  const int M = plan->p.newton;
+  const Shape& s = plan->s;   // active batch = count
+  const size_t X = (size_t)s.X, ZJ = (size_t)s.J * s.R * s.R;
+  hipStream_t st = plan->stream;
+  // source frame of every member: x_{n0-1}, or (rho = 1, c = 0)
+  NLV_HIP(plan, xp ? nlv::launch_init_x(s, st, plan->xb, xp, 3) : nlv::launch_init_x(s, st, plan->xb, nullptr, 1));
+  if (M <= 1) {
+    if (M == 0) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, plan->xb, 2));
+  } else {
+    // steps 0 .. M-2 of all members together, from and towards the source
+    NLV_CHECK(enqueue_reconstruct(plan, turns, z, plan->xb, xh, 2, 0, M - 1, nullptr, nullptr));
+  }
+  if (M >= 1) {
+    // step M-1 of each member, in order, towards the previous frame
+    ActiveGuard guard{plan, count};
+    set_active(plan, 1);
+    for (int k = 0; k < count; ++k) {
+      nlv::TurnArgs tk;
+      std::memset(&tk, 0, sizeof(tk));
+      tk.t[0] = turns.t[k];
+      const float2* prev = k == 0 ? plan->xb : xh + (k - 1) * X;
+      // with a single step, h(n, 0) = n - 1 gives the starting point as well
+      NLV_CHECK(enqueue_reconstruct(plan, tk, z + k * ZJ, prev, xh + k * X, M == 1 ? 2 : 0, M - 1, M,
+                                    nullptr, nullptr));
+    }
+  }
+  if (d_img || d_coils) {
+    float2* co = d_coils ? d_coils : plan->w.CO;
+    NLV_CHECK(coils_into(plan, xh, co));
+    if (d_img) NLV_HIP(plan, nlv::launch_image(s, st, xh, co, d_img));
+  }
+  return NLINV_OK;
+}
+
+int nlinv_reconstruct_frames(nlinv_plan plan, int32_t count, const nlinv_c64* d_z, const int32_t* h_turn,
+                             const nlinv_c64* d_xprev, nlinv_c64* d_xhat, float* d_img, nlinv_c64* d_coils) {
+  NLV_CHECK(check_plan(plan));
+  if (count < 1 || count > plan->p.batch) return fail(plan, NLINV_E_ARG, "count must be in [1, batch]");
+  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_xprev, "d_xprev", true));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img", true));
+  NLV_CHECK(check_ptr(plan, d_coils, "d_coils", true));
+  const size_t X = (size_t)plan->s.X;
+  if (d_xprev) {
+    const char* a = reinterpret_cast<const char*>(d_xprev);
+    const char* b = reinterpret_cast<const char*>(d_xhat);
+    if (a < b + (size_t)count * X * 8 && b < a + X * 8)
+      return fail(plan, NLINV_E_ARG, "d_xhat must not overlap d_xprev");
+  }
+  ActiveGuard guard{plan, plan->s.B};
+  set_active(plan, count);
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+  const float2* z = reinterpret_cast<const float2*>(d_z);
+  const float2* xp = reinterpret_cast<const float2*>(d_xprev);
+  float2* xh = reinterpret_cast<float2*>(d_xhat);
+  float2* co = reinterpret_cast<float2*>(d_coils);
+  auto body = [&] { return enqueue_frames(plan, count, turns, z, xp, xh, d_img, co); };
+  if (plan->graphs && plan->timer_kid == NLINV_KT_NONE) {
+    std::vector<uintptr_t> key = {1, (uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)d_img,
+                                  (uintptr_t)co};
+    for (int b = 0; b < count; ++b) key.push_back((uintptr_t)turns.t[b]);
+    return run_captured(plan, std::move(key), body);
+  }
+  return body();
+}
+
+int nlinv_set_batch(nlinv_plan plan, int32_t b) {
+  NLV_CHECK(check_plan(plan));
+  if (b < 1 || b > plan->p.batch) return fail(plan, NLINV_E_ARG, "batch must be in [1, plan batch]");
+  set_active(plan, b);
+  return NLINV_OK;
+}
+
+int32_t nlinv_get_batch(nlinv_plan plan) { return plan ? plan->s.B : 0; }
 
 int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat, nlinv_c64* d_y) {
   NLV_CHECK(check_plan(plan));

@@ -289,6 +289,27 @@ struct Team {
   static constexpr int LDSN = G1 * (G2 + 1);       // complex LDS slots per line (padded)
 };
 
+// Index sets of a G-point line: all G samples, the R = G/2 centred image
+// samples, or the G_c = G/4 centred coil-spectrum samples.  For each register
+// slot of a team transform the set membership of the slot's index range is
+// classified at compile time, so that absent inputs become constant zeros
+// (folded away) and unused outputs become dead code.
+enum : int { SET_ALL = 0, SET_IMG = 1, SET_COIL = 2 };
+enum : int { NEVER = 0, ALWAYS = 1, RUNTIME = 2 };
+constexpr int classify(int G, int set, int lo, int len) {
+  if (set == SET_ALL) return ALWAYS;
+  const int H = set == SET_IMG ? G / 4 : G / 8;
+  int nin = 0;
+  for (int n = lo; n < lo + len; ++n) nin += (n < H || n >= G - H) ? 1 : 0;
+  return nin == 0 ? NEVER : (nin == len ? ALWAYS : RUNTIME);
+}
+// index n = tl + G1 * N2 (tl in [0, G1)): fsA inputs, fsB outputs
+template <int G, int SET, int N2>
+constexpr int cls_n() { return classify(G, SET, Team<G>::G1 * N2, Team<G>::G1); }
+// index k = G2 * K1 + tl (tl in [0, G2)): fsA outputs, fsB inputs
+template <int G, int SET, int K1>
+constexpr int cls_k() { return classify(G, SET, Team<G>::G2 * K1, Team<G>::G2); }
+
 // runtime twiddle exp(DIR i 2 pi m / G) from the host-built FP64 table tw[m] = (cos, sin)
 template <int DIR, class C>
 __device__ __forceinline__ C twr(const double2* __restrict__ tw, int m) {
@@ -298,9 +319,10 @@ __device__ __forceinline__ C twr(const double2* __restrict__ tw, int m) {
 }
 
 // fsA: inputs x[n1 + G1 n2] from load(n) (thread tl = n1 < G1); outputs
-// X[G2 k1 + tl] in out[k1] for tl < G2.  Contains one workgroup barrier; every
-// thread of the block must call it.
-template <int G, int DIR, class C, class Load>
+// X[G2 k1 + tl] in out[k1] for tl < G2.  Inputs outside SET_IN are zero and
+// outputs outside SET_OUT are left zero.  Contains one workgroup barrier;
+// every thread of the block must call it.
+template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Load>
 __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ tw, Load&& load,
                                     C (&out)[Team<G>::G1]) {
   using T = Team<G>;
@@ -308,13 +330,24 @@ __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ 
     C a[T::G2];
     sfor<0, T::G2>([&](auto i) {
       constexpr int n2 = decltype(i)::value;
-      a[n2] = load(tl + T::G1 * n2);
+      if constexpr (cls_n<G, SET_IN, n2>() == NEVER) {
+        a[n2] = czero<C>();
+      } else {
+        a[n2] = load(tl + T::G1 * n2);
+      }
     });
     DFT<T::G2, DIR, C>::run(a);
+    // twiddles w^(tl k2) by recurrence from one table value (FP64: the
+    // rounding of the k2-fold product stays near 1e-15, far below float32)
+    const C w1 = twr<DIR, C>(tw, tl);
+    C wk = w1;
     sfor<0, T::G2>([&](auto i) {
       constexpr int k2 = decltype(i)::value;
       C v = a[k2];
-      if constexpr (k2 != 0) v = cmul(v, twr<DIR, C>(tw, tl * k2));
+      if constexpr (k2 != 0) {
+        v = cmul(v, wk);
+        if constexpr (k2 + 1 < T::G2) wk = cmul(wk, w1);
+      }
       lds[tl * (T::G2 + 1) + k2] = v;
     });
   }
@@ -325,23 +358,37 @@ __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ 
       out[n1] = lds[n1 * (T::G2 + 1) + tl];
     });
     DFT<T::G1, DIR, C>::run(out);
+    sfor<0, T::G1>([&](auto i) {
+      constexpr int k1 = decltype(i)::value;
+      if constexpr (cls_k<G, SET_OUT, k1>() == NEVER) out[k1] = czero<C>();
+    });
   }
 }
 
-// fsB: inputs x[G2 k1 + tl] in in[k1] (thread tl < G2); outputs X[n1 + G1 n2]
-// passed to store(n, value) by thread tl = n1 < G1.  Starts with a barrier so
-// that the LDS line may be reused right after fsA; contains two barriers.
-template <int G, int DIR, class C, class Store>
+// fsB: inputs x[G2 k1 + tl] in in[k1] (thread tl < G2), taken as zero outside
+// SET_IN; outputs X[n1 + G1 n2] inside SET_OUT are passed to store(n, value) by
+// thread tl = n1 < G1.  Starts with a barrier so that the LDS line may be
+// reused right after fsA; contains two barriers.
+template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Store>
 __device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ tw,
                                     C (&in)[Team<G>::G1], Store&& store) {
   using T = Team<G>;
   __syncthreads();
   if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto i) {
+      constexpr int k1 = decltype(i)::value;
+      if constexpr (cls_k<G, SET_IN, k1>() == NEVER) in[k1] = czero<C>();
+    });
     DFT<T::G1, DIR, C>::run(in);
+    const C w1 = twr<DIR, C>(tw, tl);   // w^(n1 tl) by recurrence, as in fsA
+    C wk = w1;
     sfor<0, T::G1>([&](auto i) {
       constexpr int n1 = decltype(i)::value;
       C v = in[n1];
-      if constexpr (n1 != 0) v = cmul(v, twr<DIR, C>(tw, n1 * tl));
+      if constexpr (n1 != 0) {
+        v = cmul(v, wk);
+        if constexpr (n1 + 1 < T::G1) wk = cmul(wk, w1);
+      }
       lds[n1 * (T::G2 + 1) + tl] = v;
     });
   }
@@ -355,7 +402,7 @@ __device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ 
     DFT<T::G2, DIR, C>::run(a);
     sfor<0, T::G2>([&](auto i) {
       constexpr int n2 = decltype(i)::value;
-      store(tl + T::G1 * n2, a[n2]);
+      if constexpr (cls_n<G, SET_OUT, n2>() != NEVER) store(tl + T::G1 * n2, a[n2]);
     });
   }
 }

@@ -102,6 +102,7 @@ hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int i
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
                            double alpha, float2* out);
 hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const float2* src);
+// mode 1: (rho = 1, c = 0); 2: copy xprev [B][X]; 3: broadcast xprev [X] to every item
 hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);
 hipError_t launch_image(const Shape& s, hipStream_t st, const float2* xh, const float2* co, float* img);
 hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, const float2* y,

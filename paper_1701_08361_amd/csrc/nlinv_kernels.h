@@ -121,7 +121,7 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
   const size_t off = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
   const float* dw = dinv + i * GC;
   C v[T::G1];
-  fsA<G, +1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
+  fsA<G, +1, SET_COIL, SET_IMG>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
     const int ic = coil_idx<G>(n);
     if (ic < 0) return czero<C>();
     double2 p = to_d(src[off + ic]);
@@ -168,7 +168,7 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 
   const double2* u1 = U1 + (size_t)bj * GC * R + x;
   C v[T::G1];
-  fsA<G, +1>(tl, L, tw, [&](int n) -> C {
+  fsA<G, +1, SET_COIL, SET_IMG>(tl, L, tw, [&](int n) -> C {
     const int i = coil_idx<G>(n);
     return i < 0 ? czero<C>() : u1[(size_t)i * R];
   }, v);
@@ -205,7 +205,7 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
   if constexpr (!TO_IMG) {
     if (outp == nullptr) return;   // uniform: coil synthesis only
     S2* o = static_cast<S2*>(outp) + (size_t)bj * G * R + x;
-    fsB<G, -1>(tl, L, tw, v, [&](int n, C val) { o[(size_t)n * R] = store_as<S2>(val); });
+    fsB<G, -1, SET_IMG, SET_ALL>(tl, L, tw, v, [&](int n, C val) { o[(size_t)n * R] = store_as<S2>(val); });
   }
 }
 
@@ -235,7 +235,7 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
     });
   }
   C v[T::G1];
-  fsA<G, -1>(tl, L, tw, [&](int n) -> C {
+  fsA<G, -1, SET_IMG, SET_ALL>(tl, L, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
     return ix < 0 ? czero<C>() : to_d(line[ix]);
   }, v);
@@ -245,7 +245,7 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
       v[k1] = cscale(v[k1], (double)pk[k1]);
     });
   }
-  fsB<G, +1>(tl, L, tw, v, [&](int n, C val) {
+  fsB<G, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
     const int ix = img_idx<G>(n);
     if (ix >= 0) line[ix] = store_as<S2>(val);
   });
@@ -275,7 +275,7 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   C v[T::G1];
   if constexpr (MODE != 2) {
     const S2* c0 = static_cast<const S2*>(inp) + (size_t)bj * G * R + x;
-    fsA<G, +1>(tl, L, tw, [&](int n) -> C { return to_d(c0[(size_t)n * R]); }, v);
+    fsA<G, +1, SET_ALL, SET_IMG>(tl, L, tw, [&](int n) -> C { return to_d(c0[(size_t)n * R]); }, v);
   } else {
     const float2* in = static_cast<const float2*>(inp);
     if (tl < T::G2) {
@@ -311,7 +311,7 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
     });
   }
   double2* o = U4 + (size_t)bj * GC * R + x;
-  fsB<G, -1>(tl, L, tw, v, [&](int n, C val) {
+  fsB<G, -1, SET_IMG, SET_COIL>(tl, L, tw, v, [&](int n, C val) {
     const int i = coil_idx<G>(n);
     if (i >= 0) o[(size_t)i * R] = val;
   });
@@ -343,7 +343,7 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
   const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
   const double2* line = U4 + (size_t)row * R;
   C v[T::G1];
-  fsA<G, -1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
+  fsA<G, -1, SET_IMG, SET_COIL>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
     return ix < 0 ? czero<C>() : line[ix];
   }, v);
@@ -398,7 +398,7 @@ k_fft_rows_full(double2* __restrict__ a, const double2* __restrict__ tw) {
   const int row = blockIdx.x * ROWS + rl;
   double2* line = a + (size_t)row * G;
   C v[T::G1];
-  fsA<G, -1>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C { return line[n]; }, v);
+  fsA<G, -1, SET_ALL, SET_ALL>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C { return line[n]; }, v);
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
@@ -418,7 +418,7 @@ k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const doubl
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int x = blockIdx.x * TW + col;
   C v[T::G1];
-  fsA<G, -1>(tl, lds + col * T::LDSN, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
+  fsA<G, -1, SET_ALL, SET_ALL>(tl, lds + col * T::LDSN, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;

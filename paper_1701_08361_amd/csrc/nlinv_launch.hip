@@ -176,6 +176,13 @@ k_copy(float2* __restrict__ dst, const float2* __restrict__ src, long long n) {
   if (e < n) dst[e] = src[e];
 }
 
+// dst[b][k] = src[k] for every item b.
+__global__ void __launch_bounds__(VT)
+k_bcast(float2* __restrict__ dst, const float2* __restrict__ src, long long X, long long n) {
+  const long long e = (long long)blockIdx.x * VT + threadIdx.x;
+  if (e < n) dst[e] = src[e % X];
+}
+
 // x = (rho = 1, c_hat = 0) for every item.
 __global__ void __launch_bounds__(VT)
 k_init_unit(float2* __restrict__ xh, int RR, long long X, long long n) {
@@ -437,6 +444,8 @@ hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float
   const int blocks = (int)((n + VT - 1) / VT);
   if (mode == 2) {
     k_copy<<<blocks, VT, 0, st>>>(xh, xprev, n);
+  } else if (mode == 3) {
+    k_bcast<<<blocks, VT, 0, st>>>(xh, xprev, s.X, n);
   } else {
     k_init_unit<<<blocks, VT, 0, st>>>(xh, s.R * s.R, s.X, n);
   }

@@ -58,6 +58,9 @@ def load() -> ctypes.CDLL:
         "nlinv_psf": [_P, _P, _I],
         "nlinv_grid": [_P, _P, _P, _P, _P],
         "nlinv_reconstruct": [_P, _P, _P, _P, _P, _I, _P, _P],
+        "nlinv_reconstruct_frames": [_P, _I, _P, _P, _P, _P, _P, _P],
+        "nlinv_set_batch": [_P, _I],
+        "nlinv_get_batch": [_P],
         "nlinv_apply_F": [_P, _P, _P, _P],
         "nlinv_apply_DF": [_P, _P, _P, _P, _P],
         "nlinv_apply_DFH": [_P, _P, _P, _P, _P],
@@ -71,7 +74,7 @@ def load() -> ctypes.CDLL:
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_int
+        fn.restype = ctypes.c_int32 if name == "nlinv_get_batch" else ctypes.c_int
     lib.nlinv_last_error.argtypes = [_P]
     lib.nlinv_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -82,7 +85,7 @@ def header_symbols() -> list:
     """Names of the functions declared in include/nlinv.h."""
     with open(HEADER) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(nlinv_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|const char\*)\s+(nlinv_\w+)\s*\(", text, re.M)))
 
 
 def _check(rc: int, plan=None):
@@ -127,7 +130,8 @@ class Plan:
         sz = sizes(self.params)
         self.N, self.J, self.K = N, J, K
         self.R, self.G, self.Gc, self.S, self.X = sz["R"], sz["G"], sz["Gc"], sz["S"], sz["X"]
-        self.B = self.params.batch
+        self.B = self.params.batch          # active batch (set_batch)
+        self.Bmax = self.params.batch
         self.U = self.params.U
         self.S_r = self.S // K
         self.device = torch.device(device)
@@ -222,6 +226,37 @@ class Plan:
         self._stream_sync()
         _check(self.lib.nlinv_reconstruct(self.handle, self._ptr(z), self._turns(turns), self._ptr(xprev),
                                           self._ptr(xhat), int(init), self._ptr(img), self._ptr(coils)),
+               self.handle)
+        return xhat, img, coils
+
+    def set_batch(self, b: int):
+        """Work on the first b items (1 <= b <= the plan's batch) from now on."""
+        _check(self.lib.nlinv_set_batch(self.handle, int(b)), self.handle)
+        self.B = int(self.lib.nlinv_get_batch(self.handle))
+
+    def reconstruct_frames(self, z, turns, xprev=None, xhat=None, img=None, coils=None,
+                           want_img: bool = False, want_coils: bool = False):
+        """Consecutive frames z [count][J][R][R] of one series under the relaxed
+        temporal coupling; xprev [X] is the frame before them (None: unit start)."""
+        torch = self.torch
+        J, R, X = self.J, self.R, self.X
+        count = int(z.shape[0])
+        self._t(z, torch.complex64, (count, J, R, R), "z")
+        self._t(xprev, torch.complex64, (X,), "xprev", allow_none=True)
+        xhat = self.empty(count, X) if xhat is None else xhat
+        self._t(xhat, torch.complex64, (count, X), "xhat")
+        if want_img and img is None:
+            img = self.empty(count, R, R, dtype=torch.float32)
+        if want_coils and coils is None:
+            coils = self.empty(count, J, R, R)
+        self._t(img, torch.float32, (count, R, R), "img", allow_none=True)
+        self._t(coils, torch.complex64, (count, J, R, R), "coils", allow_none=True)
+        if len(turns) != count:
+            raise ValueError("one turn per frame")
+        tt = (ctypes.c_int32 * count)(*[int(t) for t in turns])
+        self._stream_sync()
+        _check(self.lib.nlinv_reconstruct_frames(self.handle, count, self._ptr(z), tt, self._ptr(xprev),
+                                                 self._ptr(xhat), self._ptr(img), self._ptr(coils)),
                self.handle)
         return xhat, img, coils
 

@@ -1,0 +1,155 @@
+"""Frame series on the GPU: the relaxed temporal coupling (Sec. 4.2, temporal
+decomposition, equation for h(n, m)) through nlinv_reconstruct_frames, and
+partial batches through nlinv_set_batch, against the FP64 oracle and against
+the plain entry points.
+"""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1701_08361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1701_08361_amd import nlinv
+    nlinv.load()            # fails loudly when the HIP library is missing
+    return _t
+
+
+def nl():
+    from paper_1701_08361_amd import nlinv
+    return nlinv
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _grid_all(torch, plan, ser, frames):
+    """z [F][J][R][R] of the given frames, one gridding call per frame (batch 1)."""
+    out = []
+    plan.set_batch(1)
+    for f in frames:
+        out.append(plan.grid(dev(torch, ser.traj[f:f + 1]), dev(torch, ser.y[f:f + 1]), turns=[int(ser.turn[f])]))
+    plan.set_batch(plan.Bmax)
+    return torch.cat(out, 0)
+
+
+def test_frames_count1_equals_reconstruct(torch):
+    """count = 1 is the strict order: bit-identical to nlinv_reconstruct."""
+    N, J, K, U, M, C = 32, 4, 7, 2, 3, 6
+    print_case("frames count=1", N=N, J=J, K=K, M=M, C=C)
+    ser = synth.real_time_series(seed=21, N=N, J=J, J_phys=6, K=K, U=U, frames=2)
+    plan = nl().Plan(N, J, K, U=U, batch=3, newton=M, cg=C)
+    z = _grid_all(torch, plan, ser, [0, 1])
+    plan.set_batch(1)
+    x0, img0, _ = plan.reconstruct(z[0:1], [0], init=1, want_img=True)
+    x1, img1, _ = plan.reconstruct(z[1:2], [1], xprev=x0, init=2, want_img=True)
+    plan.set_batch(3)
+    for graphs in (False, True):
+        plan.set_graphs(graphs)
+        for rep in range(2 if graphs else 1):
+            f0, i0, _ = plan.reconstruct_frames(z[0:1], [0], xprev=None, want_img=True)
+            f1, i1, _ = plan.reconstruct_frames(z[1:2], [1], xprev=f0[0], want_img=True)
+            torch.cuda.synchronize()
+            assert torch.equal(f0, x0) and torch.equal(f1, x1), (graphs, rep)
+            assert torch.equal(i0, img0) and torch.equal(i1, img1), (graphs, rep)
+    plan.set_graphs(False)
+    assert plan.B == 3
+
+
+@pytest.mark.parametrize("M,l,o", [(3, 2, 3), (1, 0, 2), (2, 1, 4)])
+def test_relaxed_series_matches_oracle(torch, M, l, o):
+    """A 9-frame series under h(n, m) with groups of o frames: every frame's
+    image and coil images match the oracle's relaxed schedule."""
+    N, J, K, U, C, F = 32, 5, 7, 3, 8, 9
+    print_case("relaxed series", N=N, J=J, K=K, U=U, M=M, C=C, F=F, l=l, o=o)
+    ser = synth.real_time_series(seed=23, N=N, J=J, J_phys=8, K=K, U=U, frames=F)
+    g = O.Geometry.make(N, J)
+    src = O.relaxed_sources(F, l, o)
+    zs = [O.grid(ser.y[f], ser.traj[f], g.R) for f in range(F)]
+    Ps = [O.psf_kernel(ser.traj[f], g.R, g.G) for f in range(F)]
+    ref = O.reconstruct_series(g, zs, Ps, src, newton=M, cg_iters=C)
+
+    plan = nl().Plan(N, J, K, U=U, batch=o, newton=M, cg=C)
+    z = _grid_all(torch, plan, ser, range(F))
+    X = plan.X
+    xs = torch.empty(F, X, dtype=torch.complex64, device="cuda")
+    imgs = torch.empty(F, N, N, dtype=torch.float32, device="cuda")
+    n = 0
+    while n < F:
+        # a group: frames sharing one source (strict frames are groups of one)
+        k = 1
+        while n + k < F and src[n + k] == src[n] and n > l:
+            k += 1
+        prev = xs[n - 1] if n > 0 else None
+        assert src[n] == n - 1
+        plan.reconstruct_frames(z[n:n + k], [int(t) for t in ser.turn[n:n + k]], xprev=prev,
+                                xhat=xs[n:n + k], img=imgs[n:n + k])
+        n += k
+    xs, imgs = host(xs), host(imgs)
+    worst = 0.0
+    for f in range(F):
+        e_img = rel(imgs[f], O.image(g, ref[f]))
+        e_rc = rel(O.coil_images(g, xs[f].astype(np.complex128)), O.coil_images(g, ref[f]))
+        worst = max(worst, e_img, e_rc)
+        assert e_img < IMG_TOL and e_rc < IMG_TOL, (f, e_img, e_rc)
+    print(f"relaxed series M={M} l={l} o={o}: worst rel {worst:.2e}")
+
+
+def test_set_batch_partial_equals_smaller_plan(torch):
+    """A batch-4 plan restricted to 2 items grids and reconstructs exactly like a
+    batch-2 plan."""
+    N, J, K, U, M, C = 32, 3, 5, 2, 2, 5
+    print_case("set_batch", N=N, J=J, K=K, M=M, C=C)
+    ser = synth.real_time_series(seed=25, N=N, J=J, J_phys=4, K=K, U=U, frames=2)
+    big = nl().Plan(N, J, K, U=U, batch=4, newton=M, cg=C)
+    small = nl().Plan(N, J, K, U=U, batch=2, newton=M, cg=C)
+    big.set_batch(2)
+    turns = [int(t) for t in ser.turn[:2]]
+    traj, y = dev(torch, ser.traj[:2]), dev(torch, ser.y[:2])
+    zb = big.grid(traj, y, turns=turns)
+    zs = small.grid(traj, y, turns=turns)
+    assert torch.equal(zb, zs)
+    xb, ib, _ = big.reconstruct(zb, turns, init=1, want_img=True)
+    xs, is_, _ = small.reconstruct(zs, turns, init=1, want_img=True)
+    assert torch.equal(xb, xs) and torch.equal(ib, is_)
+
+
+def test_frames_argument_errors(torch):
+    N = nl()
+    plan = N.Plan(32, 3, 5, U=1, batch=2)
+    plan.psf(dev(torch, synth.radial_trajectory(32, 5, 64, 0, 1)), 0)
+    z = torch.zeros(3, 3, 32, 32, dtype=torch.complex64, device="cuda")
+    with pytest.raises(N.NlinvError) as ei:
+        plan.reconstruct_frames(z, [0, 0, 0])                 # count > batch
+    assert ei.value.code == N.E_ARG
+    x = torch.zeros(2, plan.X, dtype=torch.complex64, device="cuda")
+    with pytest.raises(N.NlinvError) as ei:
+        plan.reconstruct_frames(z[:2], [0, 0], xprev=x[1], xhat=x)   # overlap
+    assert ei.value.code == N.E_ARG
+    with pytest.raises(N.NlinvError) as ei:
+        plan.set_batch(3)
+    assert ei.value.code == N.E_ARG
+    assert plan.B == 2
