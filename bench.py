@@ -16,6 +16,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
@@ -29,6 +30,39 @@ if ROOT not in sys.path:
 
 N, J, J_PHYS, K, U, M, C = 160, 10, 30, 15, 5, 7, 20
 HBM_PEAK_GBS = 8000.0
+
+# rocprofv3 HBM counter summary of the roofline kernel (FETCH_SIZE / WRITE_SIZE
+# per dispatch, scaled by a plain copy of known size), and the sources it was
+# taken on: the figures are used only while those sources are unchanged.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "nlinv_toeplitz_rows_series160_pmc.md")
+KERNEL_SOURCES = ["paper_1701_08361_amd/csrc/nlinv_fft.h", "paper_1701_08361_amd/csrc/nlinv_kernels.h",
+                  "paper_1701_08361_amd/csrc/nlinv_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str):
+    """{batch: HBM bytes per launch} of kernel class `kind` from the counter
+    summary, or None if there is none for the current kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    src, out = None, {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 2 and t[0] == "kernel_sources:":
+                src = t[1]
+            elif len(t) == 5 and t[0] == "traffic:" and t[1] == kind and t[2] == "batch":
+                out[int(t[3])] = float(t[4])
+    if src != kernel_source_hash() or not out:
+        return None
+    return out
 
 
 def _series(args):
@@ -231,7 +265,11 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--relaxed-l", type=int, default=U, help="strict frames before relaxed coupling (l)")
     ap.add_argument("--relaxed-o", type=int, default=3, help="frames per relaxed group (o); 0 = skip")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -266,6 +304,7 @@ def main():
         del src, dst
 
     kbytes, kms, klaunch = 0.0, 0.0, 0
+    launches_by_batch, by_batch = {}, {}
     out = {"metric": "frames/sec + p99 frame latency, 160px 10ch NLINV, batched vs plain, 1 GPU",
            "unit": "frames/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
@@ -280,6 +319,10 @@ def main():
         kbytes += tl * kernel_bytes(args.kernel, 1, args.fast, 1)
         kms += tms
         klaunch += tl
+        launches_by_batch[1] = tl
+        if tl:
+            by_batch["1"] = {"avg_launch_us": tms / tl * 1e3,
+                             "achieved": kernel_bytes(args.kernel, 1, args.fast, 1) / (tms / tl / 1e3) / 1e9}
     if plain_data is not None and args.relaxed_o > 0 and not args.fast:
         l, o = args.relaxed_l, args.relaxed_o
         img_rel = torch.zeros_like(img_strict)
@@ -302,6 +345,10 @@ def main():
         kbytes += tl * kernel_bytes(args.kernel, B, args.fast, 1)
         kms += tms
         klaunch += tl
+        launches_by_batch[B] = launches_by_batch.get(B, 0) + tl
+        if tl:
+            by_batch[str(B)] = {"avg_launch_us": tms / tl * 1e3,
+                                "achieved": kernel_bytes(args.kernel, B, args.fast, 1) / (tms / tl / 1e3) / 1e9}
         if plain_data is None:
             out.update({"value": out["batched"]["fps"], "steps": args.batch_steps, "warmup": args.warmup,
                         "ms_per_step": out["batched"]["ms_per_step"]})
@@ -312,9 +359,17 @@ def main():
                      "data_gen_s": round(t_gen, 1)}
     if klaunch:
         achieved = kbytes / (kms / 1e3) / 1e9
+        # measured HBM bytes per launch, averaged over the same launch mix as `achieved`
+        meas = measured_traffic(args.kernel) if not args.fast else None
+        traffic = None
+        if meas is not None and all(b in meas for b in launches_by_batch):
+            traffic = sum(n * meas[b] for b, n in launches_by_batch.items()) / klaunch
         out["roofline"] = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "avg_launch_us": kms / klaunch * 1e3, "launches": klaunch}
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "algorithmic_bytes_per_launch": kbytes / klaunch,
+                           "avg_launch_us": kms / klaunch * 1e3, "launches": klaunch,
+                           "launches_by_batch": {str(b): n for b, n in launches_by_batch.items()},
+                           "by_batch": by_batch}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

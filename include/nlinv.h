@@ -143,7 +143,7 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
                       const nlinv_c64* d_xprev, nlinv_c64* d_xhat, int32_t init,
                       float* d_img, nlinv_c64* d_coils);
 
-/* Relaxed temporal coupling (Sec. 4.2, temporal decomposition, equation for
+/* Relaxed temporal coupling (Sec. 3.3, temporal decomposition, equation for
  * h(n, m)): reconstruct `count` consecutive frames n0 .. n0+count-1 of one
  * series (1 <= count <= batch) together.
  *   d_z     [count][J][R][R]  gridded data of the frames, in order

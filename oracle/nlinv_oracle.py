@@ -374,7 +374,7 @@ def coil_images(g: Geometry, x: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# frame series: strict order and relaxed temporal coupling (Sec. 4.2,
+# frame series: strict order and relaxed temporal coupling (Sec. 3.3,
 # temporal decomposition, equation for h(n, m))
 # ---------------------------------------------------------------------------
 
@@ -410,9 +410,9 @@ def reconstruct_series(g: Geometry, zs, Ps, sources: list | None = None, newton:
 
     Frame n starts from x_{h(n, 0)} and Newton step m is regularised towards
     x_{h(n, m)}, where h(n, m) = n - 1 for the last step m = M-1 and
-    h(n, m) = sources[n] for m < M-1 (equation for h(n, m), Sec. 4.2).
+    h(n, m) = sources[n] for m < M-1 (equation for h(n, m), Sec. 3.3).
     sources = None is the strict order h(n, m) = n - 1.  Frame 0 starts from
-    and is regularised towards (rho = 1, c = 0) (Sec. 4.2)."""
+    and is regularised towards (rho = 1, c = 0) (Sec. 3.3)."""
     F = len(zs)
     if sources is None:
         sources = [n - 1 for n in range(F)]

@@ -156,13 +156,13 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
   constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
   constexpr bool NORMAL = (MODE == 1 || MODE == 3);
   constexpr bool TO_IMG = (MODE == 2 || MODE == 3);
-  __shared__ C lds[TW * T::LDSN];
+  __shared__ C lds[TW * T::LDSC];
   __shared__ double sh[NTH];
   const bool act = (int)threadIdx.x < TW * T::SIZE;
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
   const int x = tile * TW + col;
-  C* L = lds + col * T::LDSN;
+  C* L = lds + col * T::LDSC;
   const bool upd = NORMAL && rsrc != nullptr;
   const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
 
@@ -263,13 +263,13 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
             double* __restrict__ part, int stride, int J, long long X) {
   using T = Team<G>;
   constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
-  __shared__ C lds[TW * T::LDSN];
+  __shared__ C lds[TW * T::LDSC];
   __shared__ double sh[NTH];
   const bool act = (int)threadIdx.x < TW * T::SIZE;
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
   const int x = tile * TW + col;
-  C* L = lds + col * T::LDSN;
+  C* L = lds + col * T::LDSC;
   const size_t img = (size_t)bj * R * R;
 
   C v[T::G1];
@@ -413,12 +413,12 @@ __global__ void __launch_bounds__(cols_threads<G>())
 k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const double2* __restrict__ tw,
                double scale) {
   using T = Team<G>;
-  __shared__ C lds[TW * T::LDSN];
+  __shared__ C lds[TW * T::LDSC];
   const bool act = (int)threadIdx.x < TW * T::SIZE;
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
   const int x = blockIdx.x * TW + col;
   C v[T::G1];
-  fsA<G, -1, SET_ALL, SET_ALL>(tl, lds + col * T::LDSN, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
+  fsA<G, -1, SET_ALL, SET_ALL>(tl, lds + col * T::LDSC, tw, [&](int n) -> C { return a[(size_t)n * G + x]; }, v);
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;

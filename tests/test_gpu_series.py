@@ -1,4 +1,4 @@
-"""Frame series on the GPU: the relaxed temporal coupling (Sec. 4.2, temporal
+"""Frame series on the GPU: the relaxed temporal coupling (Sec. 3.3, temporal
 decomposition, equation for h(n, m)) through nlinv_reconstruct_frames, and
 partial batches through nlinv_set_batch, against the FP64 oracle and against
 the plain entry points.

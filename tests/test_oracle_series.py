@@ -1,4 +1,4 @@
-"""Pins of the oracle's frame-series schedules (Sec. 4.2, temporal
+"""Pins of the oracle's frame-series schedules (Sec. 3.3, temporal
 decomposition, equation for h(n, m)).
 
 The schedule is checked against the properties the equation fixes: frames up
