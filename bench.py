@@ -24,6 +24,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -218,6 +220,79 @@ def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None):
     return ngroups * o, total, [a.elapsed_time(b) for a, b in ev], n
 
 
+def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs):
+    """S slices streamed at 1000 / period_ms frames/s each; the S frames of
+    period k arrive together at k * period_ms (after 2U untimed warm-up
+    periods that capture the graphs).
+      plain   : every frame is solved alone (batch 1) as soon as it arrives,
+                first come first served on one stream;
+      batched : when the GPU is free, the oldest pending period's frames
+                (one per slice) are solved as one batch of S.
+    Latency = completion (HIP event) - arrival.  Returns (latencies ms,
+    frames, wall ms)."""
+    B = 1 if policy == "plain" else S
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C)
+    plan.set_graphs(graphs)
+    traj = torch.from_numpy(np.stack([d[0] for d in data[:S]], axis=1)).cuda()  # [F,S,K,S_r,2]
+    y = torch.from_numpy(np.stack([d[1] for d in data[:S]], axis=1)).cuda()     # [F,S,J,S]
+    turn = data[0][2]
+    F = traj.shape[0]
+    for t in range(U):
+        plan.psf(traj[t, 0].contiguous(), t)
+    X = plan.X
+    state = torch.empty(2, S, X, dtype=torch.complex64, device="cuda")   # ping-pong per period
+    z = torch.empty(B, J, N, N, dtype=torch.complex64, device="cuda")
+    img = torch.empty(B, N, N, dtype=torch.float32, device="cuda")
+
+    def solve_period(k):
+        f = k % F
+        tn = int(turn[f])
+        cur, prev = state[k & 1], state[(k - 1) & 1]
+        if policy == "plain":
+            for s in range(S):
+                plan.grid(traj[f, s:s + 1], y[f, s:s + 1], z=z)
+                plan.reconstruct(z, [tn], xprev=None if k == 0 else prev[s:s + 1], xhat=cur[s:s + 1],
+                                 init=1 if k == 0 else 2, img=img)
+                yield s
+        else:
+            plan.grid(traj[f], y[f], z=z)
+            plan.reconstruct(z, [tn] * S, xprev=None if k == 0 else prev, xhat=cur,
+                             init=1 if k == 0 else 2, img=img)
+            yield S - 1
+
+    warm = 2 * U
+    for k in range(warm):
+        for _ in solve_period(k):
+            pass
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    done = []                          # (event, arrival ms)
+    t0 = time.perf_counter()
+    start.record()
+    last = None
+    for i in range(periods):
+        k = warm + i
+        arrival = i * period_ms
+        now = (time.perf_counter() - t0) * 1e3
+        if now < arrival:
+            time.sleep((arrival - now) / 1e3)
+        if policy == "batched" and last is not None:
+            last.synchronize()           # the GPU takes the next batch when it is free
+        for s in solve_period(k):
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            n_done = 1 if policy == "plain" else S
+            done.append((ev, arrival, n_done))
+            last = ev
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    lat = []
+    for ev, arrival, n in done:
+        lat += [start.elapsed_time(ev) - arrival] * n
+    plan.close()
+    return lat, S * periods, wall
+
+
 def pct(v, q):
     v = sorted(v)
     k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
@@ -266,6 +341,9 @@ def main():
     ap.add_argument("--relaxed-l", type=int, default=U, help="strict frames before relaxed coupling (l)")
     ap.add_argument("--relaxed-o", type=int, default=3, help="frames per relaxed group (o); 0 = skip")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--serve-slices", type=int, default=4, help="slices streamed in the serving run (0 = skip)")
+    ap.add_argument("--serve-periods", type=int, default=60, help="timed frame periods per slice")
+    ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -352,6 +430,15 @@ def main():
         if plain_data is None:
             out.update({"value": out["batched"]["fps"], "steps": args.batch_steps, "warmup": args.warmup,
                         "ms_per_step": out["batched"]["ms_per_step"]})
+    if batch_data is not None and args.serve_slices > 0 and not args.fast:
+        S = min(args.serve_slices, len(batch_data))
+        serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods}
+        for policy in ("plain", "batched"):
+            lat, nfr, wall = run_serving(torch, nl, batch_data, S, args.serve_periods, 1e3 / args.serve_fps, policy,
+                                         not args.no_graphs)
+            serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
+                               "frames": nfr, "fps": nfr / (wall / 1e3)}
+        out["serving"] = serving
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
                      "plain_batch": 1, "batched_batch": args.batch, "fast_grid": bool(args.fast),
