@@ -102,7 +102,9 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   S.U = p->U;
   S.X = (long long)S.R * S.R + (long long)S.J * S.GC * S.GC;
   S.NT = S.R / nlv::TW;
-  S.NX3 = S.J * S.GC / nlv::ROWS;
+  const nlv::GTable* tab = nlv::table_for(G);
+  if (!tab) return bad(NLINV_E_SIZE, "no kernels for this grid size");
+  S.NX3 = (S.J * S.GC + tab->row_lines - 1) / tab->row_lines;
   S.NY2 = S.J * S.NT;
   S.NCI = (S.R * S.R + nlv::CHUNK - 1) / nlv::CHUNK;
   S.NCH = (int)((S.X + nlv::CHUNK - 1) / nlv::CHUNK);

@@ -323,16 +323,13 @@ __device__ __forceinline__ C twr(const double2* __restrict__ tw, int m) {
   return CT<C>::mk((R)v.x, (R)(DIR > 0 ? v.y : -v.y));
 }
 
-// fsA: inputs x[n1 + G1 n2] from load(n) (thread tl = n1 < G1); outputs
-// X[G2 k1 + tl] in out[k1] for tl < G2.  Inputs outside SET_IN are zero and
-// outputs outside SET_OUT are left zero.  Contains one workgroup barrier;
-// every thread of the block must call it.
-template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Load>
-__device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ tw, Load&& load,
-                                    C (&out)[Team<G>::G1]) {
+// Gather of the fsA inputs of thread tl < G1: a[n2] = x[tl + G1 n2] from
+// load(n), constant zero outside SET_IN.  Split from fsA so that a kernel can
+// issue the loads of its next line group before transforming the current one.
+template <int G, int SET_IN, class C, class Load>
+__device__ __forceinline__ void fsA_load(int tl, C (&a)[Team<G>::G2], Load&& load) {
   using T = Team<G>;
   if (tl < T::G1) {
-    C a[T::G2];
     sfor<0, T::G2>([&](auto i) {
       constexpr int n2 = decltype(i)::value;
       if constexpr (cls_n<G, SET_IN, n2>() == NEVER) {
@@ -341,6 +338,17 @@ __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ 
         a[n2] = load(tl + T::G1 * n2);
       }
     });
+  }
+}
+
+// fsA on gathered inputs a (fsA_load); outputs X[G2 k1 + tl] in out[k1] for
+// tl < G2, outputs outside SET_OUT left zero.  Contains one workgroup barrier;
+// every thread of the block must call it.  a is overwritten.
+template <int G, int DIR, int SET_OUT, class C>
+__device__ __forceinline__ void fsA_regs(int tl, C* lds, const double2* __restrict__ tw,
+                                         C (&a)[Team<G>::G2], C (&out)[Team<G>::G1]) {
+  using T = Team<G>;
+  if (tl < T::G1) {
     DFT<T::G2, DIR, C>::run(a);
     // twiddles w^(tl k2) by recurrence from one table value (FP64: the
     // rounding of the k2-fold product stays near 1e-15, far below float32)
@@ -368,6 +376,18 @@ __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ 
       if constexpr (cls_k<G, SET_OUT, k1>() == NEVER) out[k1] = czero<C>();
     });
   }
+}
+
+// fsA: inputs x[n1 + G1 n2] from load(n) (thread tl = n1 < G1); outputs
+// X[G2 k1 + tl] in out[k1] for tl < G2.  Inputs outside SET_IN are zero and
+// outputs outside SET_OUT are left zero.  Contains one workgroup barrier;
+// every thread of the block must call it.
+template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Load>
+__device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ tw, Load&& load,
+                                    C (&out)[Team<G>::G1]) {
+  C a[Team<G>::G2];
+  fsA_load<G, SET_IN>(tl, a, load);
+  fsA_regs<G, DIR, SET_OUT>(tl, lds, tw, a, out);
 }
 
 // fsB: inputs x[G2 k1 + tl] in in[k1] (thread tl < G2), taken as zero outside

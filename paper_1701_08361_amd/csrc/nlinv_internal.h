@@ -27,7 +27,7 @@ struct Shape {
   int B, J, G, R, GC, S, U;
   long long X;         // unknowns per item
   int NT;              // column tiles per channel (R / TW)
-  int NX3;             // coil-adjoint row blocks per item (J * GC / ROWS)
+  int NX3;             // coil row blocks per item (ceil(J * GC / row_lines))
   int NY2;             // back-column blocks per item (J * NT)
   int NCI;             // rho-block chunks (ceil(R*R / CHUNK))
   int NCH;             // vector chunks (ceil(X / CHUNK))
@@ -88,6 +88,7 @@ struct GTable {
                            double2* out2);
   // PSF kernel: 2D FFT of the embedded PSF (w.psf) -> P (real part x scale)
   hipError_t (*psf_fft)(const Shape&, const Bufs&, hipStream_t, float* P, double scale);
+  int row_lines;   // lines per block of the coil row passes
 };
 
 // Table for grid size G, or nullptr if unsupported.

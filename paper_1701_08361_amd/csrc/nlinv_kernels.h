@@ -38,6 +38,11 @@ using C = double2;   // arithmetic type of every transform
 // and reductions only (their team lane is set past the last real lane).
 constexpr int pad64(int n) { return (n + 63) / 64 * 64; }
 template <int G> constexpr int rows_threads() { return pad64(ROWS * Team<G>::SIZE); }
+// Row passes of the solver run one wavefront per block: 64 / SIZE lines (3 at
+// G = 320), so the exchanges synchronise a single wave and many small blocks
+// share a CU (measured: Toeplitz pass 15 % faster than 8-line blocks).
+template <int G> constexpr int row_lines() { return 64 / Team<G>::SIZE > 0 ? 64 / Team<G>::SIZE : 1; }
+template <int G> constexpr int row_threads() { return pad64(row_lines<G>() * Team<G>::SIZE); }
 template <int G> constexpr int cols_threads() { return pad64(TW * Team<G>::SIZE); }
 
 // ---------------------------------------------------------------------------
@@ -104,18 +109,21 @@ __device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh)
 // spectrum row i -> R image columns.  Optional fused p = r + beta p_old.
 // ---------------------------------------------------------------------------
 template <int G, class V>
-__global__ void __launch_bounds__(rows_threads<G>())
+__global__ void __launch_bounds__(row_threads<G>())
 k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
             Partials sc, const float* __restrict__ dinv, const double2* __restrict__ tw,
-            double2* __restrict__ U1, int J, long long X) {
+            double2* __restrict__ U1, int J, long long X, int nb) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NTH = rows_threads<G>();
-  __shared__ C lds[ROWS * T::LDSN];
+  constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
+  __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[NTH];
-  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
-  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
-  const int row = blockIdx.x * ROWS + rl;
-  const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
+  // nb blocks per item, each RT of the item's J * GC lines
+  const int b = blockIdx.x / nb, chunk = blockIdx.x - b * nb;
+  const int rl0 = (int)threadIdx.x / T::SIZE, l0 = chunk * RT + rl0;
+  const bool act = rl0 < RT && l0 < J * GC;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
+  const int l = act ? l0 : 0;
+  const int i = l % GC, j = l / GC, bj = b * J + j;
   const bool upd = rsrc != nullptr;
   const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
   const size_t off = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
@@ -213,15 +221,18 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 // toep_rows: along x, FFT (R inputs) -> x P(ky, kx) -> iFFT (R outputs), in place.
 // ---------------------------------------------------------------------------
 template <int G, class S2>
-__global__ void __launch_bounds__(rows_threads<G>())
+__global__ void __launch_bounds__(row_threads<G>())
 k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
-            const double2* __restrict__ tw, int J) {
+            const double2* __restrict__ tw, int J, int nlines) {
   using T = Team<G>;
-  constexpr int R = G / 2;
-  __shared__ C lds[ROWS * T::LDSN];
-  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
-  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
-  const int row = blockIdx.x * ROWS + rl;
+  constexpr int R = G / 2, RT = row_lines<G>();
+  __shared__ C lds[RT * T::LDSN];
+  const int rl0 = (int)threadIdx.x / T::SIZE;
+  const int row0 = blockIdx.x * RT + rl0;
+  // lanes past the last team, or of a team past the last line, only take part in barriers
+  const bool act = rl0 < RT && row0 < nlines;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
+  const int row = act ? row0 : 0;
   const int ky = row % G, b = row / G / J;
   S2* line = U2 + (size_t)row * R;
   const float* prow = P + ((size_t)turns.t[b] * G + ky) * G;
@@ -328,20 +339,23 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
 // MODE 2: raw W^-H(.) -> out
 // ---------------------------------------------------------------------------
 template <int G, int MODE>
-__global__ void __launch_bounds__(rows_threads<G>())
+__global__ void __launch_bounds__(row_threads<G>())
 k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
              const double2* __restrict__ pv, const float2* __restrict__ xh, const float2* __restrict__ xprev,
              double alpha, double2* __restrict__ out, double2* __restrict__ out2,
-             double* __restrict__ part, int stride, int slot_off, int J, long long X) {
+             double* __restrict__ part, int stride, int slot_off, int J, long long X, int nb) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NTH = rows_threads<G>();
-  __shared__ C lds[ROWS * T::LDSN];
+  constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
+  __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[NTH];
-  const bool act = (int)threadIdx.x < ROWS * T::SIZE;
-  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? (int)threadIdx.x / T::SIZE : 0;
-  const int row = blockIdx.x * ROWS + rl;
-  const int i = row % GC, bj = row / GC, b = bj / J, j = bj - b * J;
-  const double2* line = U4 + (size_t)row * R;
+  // nb blocks per item, each RT of the item's J * GC lines; one partial per block
+  const int b = blockIdx.x / nb, chunk = blockIdx.x - b * nb;
+  const int rl0 = (int)threadIdx.x / T::SIZE, l0 = chunk * RT + rl0;
+  const bool act = rl0 < RT && l0 < J * GC;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
+  const int l = act ? l0 : 0;
+  const int i = l % GC, j = l / GC, bj = b * J + j;
+  const double2* line = U4 + ((size_t)bj * GC + i) * R;
   C v[T::G1];
   fsA<G, -1, SET_IMG, SET_COIL>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
@@ -378,8 +392,7 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
   }
   if constexpr (MODE != 2) {
     const double s = block_sum_waves<NTH>(acc, sh);
-    const int blocal = blockIdx.x - b * (J * GC / ROWS);
-    if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + blocal] = s;
+    if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + chunk] = s;
   }
 }
 
@@ -434,17 +447,18 @@ k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const doubl
 template <int G>
 struct GLaunch {
   static constexpr int TH_ROWS = rows_threads<G>();
+  static constexpr int TH_ROW1 = row_threads<G>();
   static constexpr int TH_COLS = cols_threads<G>();
 
   static hipError_t coil_rows(const Shape& s, const Bufs& w, hipStream_t st, const float2* src) {
-    k_coil_rows<G, float2><<<s.B * s.J * s.GC / ROWS, TH_ROWS, 0, st>>>(src, nullptr, nullptr, Partials{},
-                                                                          w.dinv, w.tw, w.U1, s.J, s.X);
+    k_coil_rows<G, float2><<<s.B * s.NX3, TH_ROW1, 0, st>>>(src, nullptr, nullptr, Partials{},
+                                                                          w.dinv, w.tw, w.U1, s.J, s.X, s.NX3);
     return hipGetLastError();
   }
   static hipError_t coil_rows_cg(const Shape& s, const Bufs& w, hipStream_t st, const double2* src,
                                  const double2* rsrc, double2* pdst, Partials sc) {
-    k_coil_rows<G, double2><<<s.B * s.J * s.GC / ROWS, TH_ROWS, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
-                                                                           w.tw, w.U1, s.J, s.X);
+    k_coil_rows<G, double2><<<s.B * s.NX3, TH_ROW1, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
+                                                                           w.tw, w.U1, s.J, s.X, s.NX3);
     return hipGetLastError();
   }
   template <class S2>
@@ -467,13 +481,16 @@ struct GLaunch {
     return s.fast ? cols_fwd_t<float2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out)
                   : cols_fwd_t<double2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out);
   }
-  static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    const int blocks = s.B * s.J * s.G / ROWS;
-    if (s.fast)
-      k_toep_rows<G, float2><<<blocks, TH_ROWS, 0, st>>>(static_cast<float2*>(w.U2), w.P, turns, w.tw, s.J);
-    else
-      k_toep_rows<G, double2><<<blocks, TH_ROWS, 0, st>>>(static_cast<double2*>(w.U2), w.P, turns, w.tw, s.J);
+  template <class S2>
+  static hipError_t toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
+    constexpr int RT = row_lines<G>();
+    const int nlines = s.B * s.J * s.G;
+    const int blocks = (nlines + RT - 1) / RT;
+    k_toep_rows<G, S2><<<blocks, row_threads<G>(), 0, st>>>(static_cast<S2*>(w.U2), w.P, turns, w.tw, s.J, nlines);
     return hipGetLastError();
+  }
+  static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
+    return s.fast ? toep_rows_t<float2>(s, w, st, turns) : toep_rows_t<double2>(s, w, st, turns);
   }
   template <class S2>
   static hipError_t cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
@@ -497,13 +514,13 @@ struct GLaunch {
   static hipError_t coilh_rows(const Shape& s, const Bufs& w, hipStream_t st, int mode, const double2* pv,
                                const float2* xh, const float2* xprev, double alpha, double2* out,
                                double2* out2) {
-    const int blocks = s.B * s.J * s.GC / ROWS;
+    const int blocks = s.B * s.NX3;
     double* part = mode == 1 ? w.rr[0] : w.pq;
     const int off = mode == 0 ? s.NY2 : 0;
     switch (mode) {
-      case 0: k_coilh_rows<G, 0><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
-      case 1: k_coilh_rows<G, 1><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
-      case 2: k_coilh_rows<G, 2><<<blocks, TH_ROWS, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X); break;
+      case 0: k_coilh_rows<G, 0><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
+      case 1: k_coilh_rows<G, 1><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
+      case 2: k_coilh_rows<G, 2><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -521,7 +538,7 @@ template <int G>
 constexpr GTable make_table() {
   return GTable{&GLaunch<G>::coil_rows, &GLaunch<G>::coil_rows_cg, &GLaunch<G>::cols_fwd,
                 &GLaunch<G>::toep_rows, &GLaunch<G>::cols_back, &GLaunch<G>::coilh_rows,
-                &GLaunch<G>::psf_fft};
+                &GLaunch<G>::psf_fft, row_lines<G>()};
 }
 
 }  // namespace nlv
