@@ -125,21 +125,45 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
   const int l = act ? l0 : 0;
   const int i = l % GC, j = l / GC, bj = b * J + j;
   const bool upd = rsrc != nullptr;
-  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
   const size_t off = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
   const float* dw = dinv + i * GC;
+  // the element loads are issued before the scalar reduction, so that both
+  // memory round trips overlap
+  C a[T::G2], ra[T::G2];
+  float wv[T::G2];
+  if (tl < T::G1) {
+    sfor<0, T::G2>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
+      a[n2] = czero<C>();
+      if constexpr (cls_n<G, SET_COIL, n2>() != NEVER) {
+        const int ic = coil_idx<G>(tl + T::G1 * n2);
+        if (ic >= 0) {
+          a[n2] = to_d(src[off + ic]);
+          if (upd) ra[n2] = rsrc[off + ic];
+          wv[n2] = dw[ic];
+        }
+      }
+    });
+  }
+  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
+  if (tl < T::G1) {
+    sfor<0, T::G2>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
+      if constexpr (cls_n<G, SET_COIL, n2>() != NEVER) {
+        const int ic = coil_idx<G>(tl + T::G1 * n2);
+        if (ic >= 0) {
+          double2 p = a[n2];
+          if (upd) {
+            p = make_double2(ra[n2].x + beta * p.x, ra[n2].y + beta * p.y);
+            pdst[off + ic] = p;
+          }
+          a[n2] = cscale(p, (double)wv[n2]);
+        }
+      }
+    });
+  }
   C v[T::G1];
-  fsA<G, +1, SET_COIL, SET_IMG>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
-    const int ic = coil_idx<G>(n);
-    if (ic < 0) return czero<C>();
-    double2 p = to_d(src[off + ic]);
-    if (upd) {
-      const double2 r = rsrc[off + ic];
-      p = make_double2(r.x + beta * p.x, r.y + beta * p.y);
-      pdst[off + ic] = p;
-    }
-    return cscale(p, (double)dw[ic]);
-  }, v);
+  fsA_regs<G, +1, SET_IMG>(tl, lds + rl * T::LDSN, tw, a, v);
   if (tl < T::G2) {
     double2* o = U1 + ((size_t)bj * GC + i) * R;
     sfor<0, T::G1>([&](auto c) {
@@ -172,38 +196,62 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
   const int x = tile * TW + col;
   C* L = lds + col * T::LDSC;
   const bool upd = NORMAL && rsrc != nullptr;
-  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
 
+  // every load of the pass is issued before the first reduction or exchange,
+  // so that their latencies overlap (one memory round trip per pass)
   const double2* u1 = U1 + (size_t)bj * GC * R + x;
-  C v[T::G1];
-  fsA<G, +1, SET_COIL, SET_IMG>(tl, L, tw, [&](int n) -> C {
+  C a[T::G2];
+  fsA_load<G, SET_COIL>(tl, a, [&](int n) -> C {
     const int i = coil_idx<G>(n);
     return i < 0 ? czero<C>() : u1[(size_t)i * R];
-  }, v);
-
+  });
   const float2* rho = xh + (size_t)b * X;
   float2* cj = co + (size_t)bj * R * R;
+  float2 rv[T::G1], cv[T::G1];
+  double2 dv[T::G1], qv[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+        const int iy = img_idx<G>(T::G2 * k1 + tl);
+        if (iy >= 0) {
+          const size_t e = (size_t)iy * R + x;
+          rv[k1] = rho[e];
+          if constexpr (NORMAL) {
+            const size_t pe = (size_t)b * X + e;
+            cv[k1] = cj[e];
+            dv[k1] = psrc[pe];
+            if (upd) qv[k1] = rsrc[pe];
+          }
+        }
+      }
+    });
+  }
+  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
+  C v[T::G1];
+  fsA_regs<G, +1, SET_IMG>(tl, L, tw, a, v);
+
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
       const int iy = img_idx<G>(T::G2 * k1 + tl);
       C u = czero<C>();
-      if (iy >= 0) {
+      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) {
         const size_t e = (size_t)iy * R + x;
-        const C r = to_d(rho[e]);
+        const C r = to_d(rv[k1]);
         if constexpr (!NORMAL) {
           const float2 cf = to_f(v[k1]);
           cj[e] = cf;
           u = cmul(r, to_d(cf));   // the stored (float32) coil image, as later passes read it
         } else {
           const size_t pe = (size_t)b * X + e;
-          double2 dr = psrc[pe];
+          double2 dr = dv[k1];
           if (upd) {
-            const double2 rr = rsrc[pe];
+            const double2 rr = qv[k1];
             dr = make_double2(rr.x + beta * dr.x, rr.y + beta * dr.y);
             if (j == 0) pdst[pe] = dr;
           }
-          u = cadd(cmul(to_d(cj[e]), dr), cmul(r, v[k1]));
+          u = cadd(cmul(to_d(cv[k1]), dr), cmul(r, v[k1]));
         }
         if constexpr (TO_IMG) static_cast<float2*>(outp)[(size_t)bj * R * R + e] = to_f(u);
       }
@@ -356,6 +404,28 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
   const int l = act ? l0 : 0;
   const int i = l % GC, j = l / GC, bj = b * J + j;
   const double2* line = U4 + ((size_t)bj * GC + i) * R;
+  const size_t base = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
+  const float* dw = dinv + i * GC;
+  // loads of the output terms are issued together with the line loads
+  float wv[T::G1];
+  double2 pvv[T::G1];
+  float2 xv[T::G1], xpv[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_COIL, k1>() != NEVER) {
+        const int ic = coil_idx<G>(T::G2 * k1 + tl);
+        if (ic >= 0) {
+          wv[k1] = dw[ic];
+          if constexpr (MODE == 0) pvv[k1] = pv[base + ic];
+          if constexpr (MODE == 1) {
+            xv[k1] = xh[base + ic];
+            xpv[k1] = xprev ? xprev[base + ic] : make_float2(0.f, 0.f);
+          }
+        }
+      }
+    });
+  }
   C v[T::G1];
   fsA<G, -1, SET_IMG, SET_COIL>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
@@ -363,29 +433,25 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
   }, v);
   double acc = 0.0;
   if (tl < T::G2) {
-    const size_t base = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
-    const float* dw = dinv + i * GC;
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
       const int ic = coil_idx<G>(T::G2 * k1 + tl);
-      if (ic >= 0) {
+      if (cls_k<G, SET_COIL, k1>() != NEVER && ic >= 0) {
         const size_t e = base + ic;
-        const double2 wv = cscale(v[k1], (double)dw[ic]);
+        const double2 w = cscale(v[k1], (double)wv[k1]);
         if constexpr (MODE == 0) {
-          const double2 p = pv[e];
-          const double2 q = make_double2(wv.x + alpha * p.x, wv.y + alpha * p.y);
+          const double2 p = pvv[k1];
+          const double2 q = make_double2(w.x + alpha * p.x, w.y + alpha * p.y);
           out[e] = q;
           acc += p.x * q.x + p.y * q.y;
         } else if constexpr (MODE == 1) {
-          const float2 xv = xh[e];
-          const float2 xp = xprev ? xprev[e] : make_float2(0.f, 0.f);
-          const double2 bv = make_double2(wv.x - alpha * ((double)xv.x - xp.x),
-                                          wv.y - alpha * ((double)xv.y - xp.y));
+          const double2 bv = make_double2(w.x - alpha * ((double)xv[k1].x - xpv[k1].x),
+                                          w.y - alpha * ((double)xv[k1].y - xpv[k1].y));
           out[e] = bv;
           out2[e] = bv;
           acc += bv.x * bv.x + bv.y * bv.y;
         } else {
-          out[e] = wv;
+          out[e] = w;
         }
       }
     });
