@@ -97,11 +97,43 @@ __device__ __forceinline__ double block_sum_array_waves(const double* __restrict
   return block_sum_waves<NT>(s, sh);
 }
 
+// Two block sums with one pair of barriers; sh holds at least 2 NT / 64 values.
+// Each sum is formed in the same order as block_sum_waves would form it.
+template <int NT>
+__device__ __forceinline__ double2 block_sum2_waves(double u, double v, double* sh) {
+  static_assert(NT % 64 == 0, "whole wavefronts only");
+  constexpr int NW = NT / 64;
+  for (int off = 32; off > 0; off >>= 1) {
+    u += __shfl_down(u, off, 64);
+    v += __shfl_down(v, off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = u;
+    sh[NW + (threadIdx.x >> 6)] = v;
+  }
+  __syncthreads();
+  double su = 0.0, sv = 0.0;
+  for (int i = 0; i < NW; ++i) su += sh[i];
+  for (int i = 0; i < NW; ++i) sv += sh[NW + i];
+  return make_double2(su, sv);
+}
+
+// Sums of two partial arrays; all loads are issued before the reduction.
+template <int NT>
+__device__ __forceinline__ double2 block_sum2_arrays_waves(const double* __restrict__ p, int n,
+                                                           const double* __restrict__ q, int m, double* sh) {
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+  for (int i = threadIdx.x; i < m; i += NT) t += q[i];
+  return block_sum2_waves<NT>(s, t, sh);
+}
+
 template <int NT>
 __device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh) {
-  const double rc = block_sum_array_waves<NT>(sc.cur + (size_t)b * sc.stride, sc.ncur, sh);
-  const double rp = block_sum_array_waves<NT>(sc.prev + (size_t)b * sc.stride, sc.nprev, sh);
-  return rp != 0.0 ? rc / rp : 0.0;
+  const double2 r = block_sum2_arrays_waves<NT>(sc.cur + (size_t)b * sc.stride, sc.ncur,
+                                                sc.prev + (size_t)b * sc.stride, sc.nprev, sh);
+  return r.y != 0.0 ? r.x / r.y : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -102,8 +102,9 @@ k_cg_update(const float2* __restrict__ PR, const double2* __restrict__ Q, const 
       }
     }
   }
-  const double pqs = block_sum_array_waves<VT>(pq + (size_t)b * rr.stride, npq, sh);
-  const double rrs = block_sum_array_waves<VT>(rr.cur + (size_t)b * rr.stride, rr.ncur, sh);
+  const double2 sums = block_sum2_arrays_waves<VT>(pq + (size_t)b * rr.stride, npq,
+                                                   rr.cur + (size_t)b * rr.stride, rr.ncur, sh);
+  const double pqs = sums.x, rrs = sums.y;
   const double a = pqs != 0.0 ? rrs / pqs : 0.0;
   double acc = 0.0;
 #pragma unroll

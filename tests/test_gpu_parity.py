@@ -277,8 +277,8 @@ def test_state_and_argument_errors(torch):
 @pytest.fixture(scope="module")
 def c2_oracle():
     """Oracle reconstructions of frames 0 and 1 of the 160 px series (frame 1
-    regularised to and started from frame 0)."""
-    ser = synth.real_time_series(seed=2, frames=2)
+    regularised to and started from frame 0); the series has 3 frames."""
+    ser = synth.real_time_series(seed=2, frames=3)
     g = O.Geometry.make(160, 10)
     out, prev = [], None
     for f in range(2):
@@ -304,3 +304,46 @@ def test_real_time_series_first_frames_c2(torch, c2_oracle, flags):
         print(f"c2 flags={flags} frame {f}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}", flush=True)
         assert e_img < IMG_TOL and e_rc < IMG_TOL
         x_prev_gpu = x.clone()
+
+
+def test_relaxed_group_c2(torch, c2_oracle):
+    """Full size, relaxed coupling with l = 0, o = 2: frame 0 strict, frames 1 and
+    2 as one group from frame 0 (nlinv_reconstruct_frames, the bench's entry
+    point).  Frame 1 heads the group, so its oracle result is the strict one;
+    frame 2 takes M-1 steps from frame 0 and the last step towards frame 1."""
+    print_case("relaxed group c2", N=160, J=10, K=15, M=7, C=20, l=0, o=2)
+    ser, g, refs = c2_oracle
+    P2 = O.psf_kernel(ser.traj[2], g.R, g.G)
+    z2 = O.grid(ser.y[2], ser.traj[2], g.R)
+    x = O.reconstruct(g, z2, P2, xprev=refs[0], x0=refs[0], newton=6, cg_iters=20)
+    ref2 = x + O.newton_step(g, x, refs[1], z2, P2, O.alpha_schedule(7)[6], 20)
+    plan = nl().Plan(160, 10, 15, U=5, batch=2, newton=7, cg=20)
+    plan.set_batch(1)
+    zs = [plan.grid(dev(torch, ser.traj[f:f + 1]), dev(torch, ser.y[f:f + 1]), turns=[int(ser.turn[f])])
+          for f in range(3)]
+    plan.set_batch(2)
+    x0, i0, _ = plan.reconstruct_frames(zs[0], [int(ser.turn[0])], want_img=True)
+    xg, ig, _ = plan.reconstruct_frames(torch.cat(zs[1:], 0), [int(t) for t in ser.turn[1:3]],
+                                        xprev=x0[0], want_img=True)
+    for f, (xf, imf, ref) in enumerate([(x0[0], i0[0], refs[0]), (xg[0], ig[0], refs[1]), (xg[1], ig[1], ref2)]):
+        e_img, e_rc = _recon_compare(g, host(xf), host(imf), ref)
+        print(f"relaxed c2 frame {f}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}", flush=True)
+        assert e_img < IMG_TOL and e_rc < IMG_TOL
+
+
+def test_batched_items_equal_plain_c2(torch, c2_oracle):
+    """Full size, batched launch configuration: every item of a batch-16 plan
+    reconstructs exactly (bit for bit) what the batch-1 plan does on the same
+    gridded data, so the batch-1 oracle parity carries over to each item."""
+    print_case("batched c2 items", N=160, J=10, K=15, M=7, C=20, B=16)
+    ser, g, refs = c2_oracle
+    one = nl().Plan(160, 10, 15, U=5, newton=7, cg=20)
+    t = int(ser.turn[0])
+    z = one.grid(dev(torch, ser.traj[0:1]), dev(torch, ser.y[0:1]), turns=[t])
+    x1, i1, _ = one.reconstruct(z, [t], want_img=True)
+    many = nl().Plan(160, 10, 15, U=5, batch=16, newton=7, cg=20)
+    many.psf(dev(torch, ser.traj[0]), t)
+    zb = z.expand(16, -1, -1, -1).contiguous()
+    xb, ib, _ = many.reconstruct(zb, [t] * 16, want_img=True)
+    for b in (0, 7, 15):
+        assert torch.equal(xb[b], x1[0]) and torch.equal(ib[b], i1[0]), b
