@@ -3,8 +3,9 @@
 Workload: the real-time series of 160 px frames (320 x 320 grid), 10 virtual
 coils (PCA from 30), 15 spokes x 320 samples per frame in 5 rotated turns,
 7 Newton x 20 CG steps, temporal regularisation to the previous frame.
-A step is one frame per series: gridding (z = F^H y, plus the PSF kernel the
-first time a turn is seen) and the IRGNM reconstruction.
+A step is one frame per series: gridding (z = F^H y by Kaiser-Bessel gridding
+through the turn's table; the PSF kernel and the table of each turn are built
+once at set-up) and the IRGNM reconstruction.
 
   plain   : one series, frames solved one after another (batch 1)  -> `value`
   batched : 16 independent series advanced together (batch 16)    -> `batched`
@@ -122,7 +123,7 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, g
     def frame(n, xprev, xout):
         f = n % F
         tn = [int(turn[f])] * B
-        plan.grid(traj[f], y[f], z=z)
+        plan.grid(traj[f], y[f], turns=tn, z=z)
         plan.reconstruct(z, tn, xprev=xprev, xhat=xout, init=(1 if xprev is None else 2), img=img)
         if img_store is not None and n < img_store.shape[0]:
             img_store[n].copy_(img[0])
@@ -184,9 +185,9 @@ def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None):
         fs = [(n + i) % F for i in range(k)]
         plan.set_batch(k)
         if fs == list(range(fs[0], fs[0] + k)):
-            plan.grid(traj[fs[0]:fs[0] + k], y[fs[0]:fs[0] + k], z=zs[k])
+            plan.grid(traj[fs[0]:fs[0] + k], y[fs[0]:fs[0] + k], turns=[int(turn[f]) for f in fs], z=zs[k])
         else:
-            plan.grid(traj[fs].contiguous(), y[fs].contiguous(), z=zs[k])
+            plan.grid(traj[fs].contiguous(), y[fs].contiguous(), turns=[int(turn[f]) for f in fs], z=zs[k])
         plan.set_batch(o)
         out = xb[state["par"]][:k]
         plan.reconstruct_frames(zs[k], [int(turn[f]) for f in fs], xprev=state["prev"], xhat=out, img=imgs[k])
@@ -250,12 +251,12 @@ def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs):
         cur, prev = state[k & 1], state[(k - 1) & 1]
         if policy == "plain":
             for s in range(S):
-                plan.grid(traj[f, s:s + 1], y[f, s:s + 1], z=z)
+                plan.grid(traj[f, s:s + 1], y[f, s:s + 1], turns=[tn], z=z)
                 plan.reconstruct(z, [tn], xprev=None if k == 0 else prev[s:s + 1], xhat=cur[s:s + 1],
                                  init=1 if k == 0 else 2, img=img)
                 yield s
         else:
-            plan.grid(traj[f], y[f], z=z)
+            plan.grid(traj[f], y[f], turns=[tn] * S, z=z)
             plan.reconstruct(z, [tn] * S, xprev=None if k == 0 else prev, xhat=cur,
                              init=1 if k == 0 else 2, img=img)
             yield S - 1

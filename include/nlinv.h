@@ -71,8 +71,11 @@ enum {
  *   Halves that buffer's HBM traffic; CG amplifies the extra rounding, so
  *   reconstructions drift further from the float64 reference (the default
  *   keeps every operator intermediate except the coil images and the
- *   per-channel products in float64). */
-enum { NLINV_F_FAST = 1 };
+ *   per-channel products in float64).
+ * NLINV_F_EXACT_GRID: nlinv_grid always forms the exact sum (see
+ *   nlinv_grid); without it, calls that name the turns use Kaiser-Bessel
+ *   gridding through per-turn tables. */
+enum { NLINV_F_FAST = 1, NLINV_F_EXACT_GRID = 2 };
 
 /* Plan parameters.  nlinv_params_default fills the defaults noted here. */
 typedef struct {
@@ -119,12 +122,20 @@ int nlinv_set_stream(nlinv_plan plan, void* stream);
  * P = unnormalised 2D DFT of psf on the G-grid; P is real and is cached in the
  * workspace under `turn` (0 <= turn < U).  d_traj: [K][S_r][2]. */
 int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn);
+/* (also builds the turn's gridding table; copies d_traj to the host and
+ * blocks until the table is in the workspace) */
 
 /* Gridding (Sec. 3.1, preprocessing): z_j = F^H y_j on the R x R field of view,
- * z_j(r) = (1/R) sum_s y_{j,s} exp(+i 2 pi k_s . r), exact sum.
+ * z_j(r) = (1/R) sum_s y_{j,s} exp(+i 2 pi k_s . r).
  * d_traj [B][K][S_r][2], d_y [B][J][S] -> d_z [B][J][R][R].
- * If h_turn != NULL (host [B]), the PSF kernel of every turn h_turn[b] not yet
- * cached is computed from d_traj[b] (as nlinv_psf). */
+ * h_turn == NULL: the exact sum over the samples of d_traj[b].
+ * h_turn != NULL (host [B]): item b is sampled on the trajectory of turn
+ * h_turn[b].  The PSF kernel and the gridding table of every turn not yet
+ * cached are computed from d_traj[b] (as nlinv_psf; this blocks the host).
+ * Unless the plan has NLINV_F_EXACT_GRID, z is then formed by Kaiser-Bessel
+ * gridding (width 9, oversampling G/R = 2; Beatty et al. 2005): gather onto
+ * the G x G grid, inverse 2D FFT, crop, deapodise; relative error ~1e-8
+ * against the exact sum, below float32 rounding. */
 int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y,
                const int32_t* h_turn, nlinv_c64* d_z);
 

@@ -64,9 +64,85 @@ bool supported_grid(int G) {
   return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 448;
 }
 
+// Kaiser-Bessel gridding kernel (Beatty, Nishimura, Pauly 2005): width W grid
+// cells at oversampling G / R = 2, shape beta = pi sqrt((W/2)^2 (2 - 1/2)^2 - 0.8).
+constexpr int KB_W = 9;
+constexpr int KB_TAPS = KB_W + 1;   // grid points a sample can reach per axis
+
+double bessel_i0(double x) {        // power series sum_k ((x/2)^k / k!)^2
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+double kb_beta() {
+  const double sigma = 2.0, hw = KB_W / sigma;
+  return M_PI * std::sqrt(hw * hw * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+}
+
+// kernel value at distance d (grid cells), normalised to 1 at d = 0
+double kb_phi(double d, double beta) {
+  const double t = 1.0 - (2.0 * d / KB_W) * (2.0 * d / KB_W);
+  return t < 0.0 ? 0.0 : bessel_i0(beta * std::sqrt(t)) / bessel_i0(beta);
+}
+
+// its continuous Fourier transform at u cycles per grid cell (|pi W u| < beta)
+double kb_phi_hat(double u, double beta) {
+  const double a = std::sqrt(beta * beta - (M_PI * KB_W * u) * (M_PI * KB_W * u));
+  return KB_W * std::sinh(a) / a / bessel_i0(beta);
+}
+
+// Gather table of one trajectory: for every grid point p = uy * G + ux of the
+// G x G grid (DC at 0, periodic), the samples s within half a kernel width on
+// both axes and their weights phi(ux - G kx_s) phi(uy - G ky_s).  Entries of a
+// grid point are in sample order.
+void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector<int2>& ent) {
+  const double beta = kb_beta();
+  struct Tap { int p; float w; };
+  std::vector<Tap> taps;
+  taps.reserve((size_t)S * KB_TAPS * KB_TAPS);
+  std::vector<int> owner;
+  owner.reserve(taps.capacity());
+  for (int s = 0; s < S; ++s) {
+    const double x = (double)G * traj[2 * s], y = (double)G * traj[2 * s + 1];
+    const int ux0 = (int)std::ceil(x - 0.5 * KB_W), uy0 = (int)std::ceil(y - 0.5 * KB_W);
+    double wx[KB_TAPS], wy[KB_TAPS];
+    for (int a = 0; a < KB_TAPS; ++a) {
+      wx[a] = kb_phi(ux0 + a - x, beta);
+      wy[a] = kb_phi(uy0 + a - y, beta);
+    }
+    for (int by = 0; by < KB_TAPS; ++by) {
+      if (wy[by] == 0.0) continue;
+      const int py = ((uy0 + by) % G + G) % G;
+      for (int bx = 0; bx < KB_TAPS; ++bx) {
+        if (wx[bx] == 0.0) continue;
+        const int px = ((ux0 + bx) % G + G) % G;
+        taps.push_back(Tap{py * G + px, (float)(wy[by] * wx[bx])});
+        owner.push_back(s);
+      }
+    }
+  }
+  const size_t GG = (size_t)G * G;
+  rp.assign(GG + 1, 0);
+  for (const Tap& t : taps) ++rp[t.p + 1];
+  for (size_t p = 0; p < GG; ++p) rp[p + 1] += rp[p];
+  std::vector<int> fill(rp.begin(), rp.end() - 1);
+  ent.resize(taps.size());
+  for (size_t k = 0; k < taps.size(); ++k) {
+    int w;
+    std::memcpy(&w, &taps[k].w, 4);
+    ent[fill[taps[k].p]++] = make_int2(owner[k], w);
+  }
+}
+
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBC, KG, total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -85,7 +161,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (p->batch < 1 || p->batch > nlv::MAXB) return bad(NLINV_E_ARG, "batch must be in [1, 64]");
   if (p->newton < 0 || p->newton > 1000) return bad(NLINV_E_ARG, "newton must be in [0, 1000]");
   if (p->cg < 1 || p->cg > 100000) return bad(NLINV_E_ARG, "cg must be in [1, 100000]");
-  if (p->flags & ~NLINV_F_FAST) return bad(NLINV_E_ARG, "unknown flag bits");
+  if (p->flags & ~(NLINV_F_FAST | NLINV_F_EXACT_GRID)) return bad(NLINV_E_ARG, "unknown flag bits");
   if (!(p->alpha0 > 0.0) || !std::isfinite(p->alpha0)) return bad(NLINV_E_ARG, "alpha0 must be positive and finite");
   if (!(p->alpha_q > 0.0 && p->alpha_q <= 1.0)) return bad(NLINV_E_ARG, "alpha_q must be in (0, 1]");
   if (!(p->alpha_min >= 0.0) || !std::isfinite(p->alpha_min)) return bad(NLINV_E_ARG, "alpha_min must be >= 0");
@@ -114,6 +190,12 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   S.stride = st;
   S.fast = (p->flags & NLINV_F_FAST) != 0;
   S.gsplit = nlv::grid_nsplit(S.B, S.J, S.R);
+  // Kaiser-Bessel gridding tables: (W + 1)^2 entries per sample and turn; left
+  // out (exact gridding only) when they would take more than 2 GiB
+  S.kbe_stride = (long long)S.S * KB_TAPS * KB_TAPS;
+  const double kb_bytes = (double)S.U * ((double)G * G + 1 + 2.0 * S.kbe_stride) * 4.0 +
+                          (double)S.B * S.J * G * G * 8.0;
+  S.kb = (p->flags & NLINV_F_EXACT_GRID) == 0 && kb_bytes <= 2147483648.0;
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -149,6 +231,10 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->rr0 = take(B * (size_t)S.stride * 8);
   L->rr1 = take(B * (size_t)S.stride * 8);
   L->XB = take(B * X * c8);
+  L->KBR = take(S.kb ? (size_t)S.U * ((size_t)Gs * Gs + 1) * 4 : 0);
+  L->KBE = take(S.kb ? (size_t)S.U * (size_t)S.kbe_stride * 8 : 0);
+  L->KBC = take(S.kb ? R * 4 : 0);
+  L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
   L->total = off;
   return NLINV_OK;
 }
@@ -219,6 +305,31 @@ int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
             return plan->t->cols_fwd(s, plan->w, plan->stream, 0, co, xh, nullptr, nullptr, nullptr,
                                         none, nullptr);
           }));
+  return NLINV_OK;
+}
+
+// PSF kernel and (if enabled) Kaiser-Bessel gridding table of one turn from
+// its trajectory (device, [K][S_r][2]).  The table is built on the host, so
+// this waits for the trajectory copy and the upload.
+int build_turn(nlinv_plan plan, const float* d_traj, int turn) {
+  const Shape& s = plan->s;
+  NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj, turn));
+  if (s.kb) {
+    std::vector<float> traj((size_t)s.S * 2);
+    NLV_HIP(plan, hipMemcpyAsync(traj.data(), d_traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                 plan->stream));
+    NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+    std::vector<int> rp;
+    std::vector<int2> ent;
+    kb_table(traj.data(), s.S, s.G, rp, ent);
+    if ((long long)ent.size() > s.kbe_stride) return fail(plan, NLINV_E_SIZE, "gridding table overflow");
+    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbr + (size_t)turn * ((size_t)s.G * s.G + 1), rp.data(),
+                                 rp.size() * sizeof(int), hipMemcpyHostToDevice, plan->stream));
+    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbe + (size_t)turn * s.kbe_stride, ent.data(), ent.size() * sizeof(int2),
+                                 hipMemcpyHostToDevice, plan->stream));
+    NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+  }
+  plan->psf_valid[turn] = 1;
   return NLINV_OK;
 }
 
@@ -327,6 +438,10 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.rr[0] = reinterpret_cast<double*>(base + L.rr0);
   w.rr[1] = reinterpret_cast<double*>(base + L.rr1);
   plan->xb = reinterpret_cast<float2*>(base + L.XB);
+  w.kbr = reinterpret_cast<int*>(base + L.KBR);
+  w.kbe = reinterpret_cast<int2*>(base + L.KBE);
+  w.kbc = reinterpret_cast<float*>(base + L.KBC);
+  w.KG = reinterpret_cast<float2*>(base + L.KG);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -342,9 +457,16 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
       dinv[(size_t)i * s.GC + ic] = (float)(1.0 / (s.G * wgt));
     }
   }
+  // deapodisation of the Kaiser-Bessel gridding, 1 / (sqrt(R) c(r)) per axis
+  std::vector<float> kbc(s.R);
+  const double beta = kb_beta();
+  for (int i = 0; i < s.R; ++i)
+    kbc[i] = (float)(1.0 / (std::sqrt((double)s.R) * kb_phi_hat((double)(i - s.R / 2) / s.G, beta)));
   hipError_t e = hipMemcpyAsync(w.tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, plan->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(w.dinv, dinv.data(), dinv.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
+  if (e == hipSuccess && s.kb)
+    e = hipMemcpyAsync(w.kbc, kbc.data(), kbc.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) {
     std::string m = std::string("HIP error uploading tables: ") + hipGetErrorString(e);
@@ -374,9 +496,7 @@ int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn) {
   NLV_CHECK(check_plan(plan));
   NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
   if (turn < 0 || turn >= plan->s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
-  NLV_HIP(plan, nlv::launch_psf(plan->s, plan->w, plan->stream, d_traj, turn));
-  plan->psf_valid[turn] = 1;
-  return NLINV_OK;
+  return build_turn(plan, d_traj, turn);
 }
 
 int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const int32_t* h_turn,
@@ -392,8 +512,17 @@ int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const
     for (int b = 0; b < s.B; ++b) {
       const int t = h_turn[b];
       if (plan->psf_valid[t]) continue;
-      NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj + (size_t)b * s.S * 2, t));
-      plan->psf_valid[t] = 1;
+      NLV_CHECK(build_turn(plan, d_traj + (size_t)b * s.S * 2, t));
+    }
+    if (s.kb) {
+      nlv::TurnArgs turns;
+      std::memset(&turns, 0, sizeof(turns));
+      for (int b = 0; b < s.B; ++b) turns.t[b] = h_turn[b];
+      NLV_HIP(plan, timed(plan, NLINV_KT_GRID, [&] {
+                return plan->t->kb_grid(s, plan->w, plan->stream, turns, reinterpret_cast<const float2*>(d_y),
+                                        reinterpret_cast<float2*>(d_z));
+              }));
+      return NLINV_OK;
     }
   }
   NLV_HIP(plan, timed(plan, NLINV_KT_GRID, [&] {

@@ -34,6 +34,8 @@ struct Shape {
   int stride;          // partial slots per item
   bool fast;           // U2 stored in float32 instead of float64
   int gsplit;          // sample-range split of the gridding kernel (1 = none)
+  bool kb;             // Kaiser-Bessel gridding tables present
+  long long kbe_stride;  // table entries per turn
 };
 
 // Gridding work decomposition (channels per block; sample-range split).
@@ -58,6 +60,10 @@ struct Bufs {
   double2* Q;     // [B][X] operator output (coil block)
   double* pq;     // [B][stride]
   double* rr[2];  // [B][stride] ping-pong
+  int* kbr;       // [U][G*G+1] gridding table row starts (per grid point)
+  int2* kbe;      // [U][kbe_stride] (sample index, weight bits) per table entry
+  float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
+  float2* KG;     // [B][J][G][G] gridded samples
 };
 
 // Grid-size specific launchers (one table per supported G).
@@ -88,6 +94,9 @@ struct GTable {
                            double2* out2);
   // PSF kernel: 2D FFT of the embedded PSF (w.psf) -> P (real part x scale)
   hipError_t (*psf_fft)(const Shape&, const Bufs&, hipStream_t, float* P, double scale);
+  // Kaiser-Bessel gridding of y [B][J][S] into z [B][J][R][R] with the turn tables
+  hipError_t (*kb_grid)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns, const float2* y,
+                        float2* z);
   int row_lines;   // lines per block of the coil row passes
 };
 

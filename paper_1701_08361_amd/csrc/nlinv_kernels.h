@@ -539,6 +539,106 @@ k_fft_cols_psf(const double2* __restrict__ a, float* __restrict__ P, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// Kaiser-Bessel gridding of the data (z_j = F^H y_j to within the kernel's
+// error): gather onto the G x G grid through the per-turn table, inverse FFT
+// of the rows (keep R columns), inverse FFT of the columns (keep R rows) with
+// the deapodisation 1 / (R c(x) c(y)).
+// ---------------------------------------------------------------------------
+
+// g[b][j][p] = sum over table row p of w * y[b][j][s]; one thread per grid point,
+// channels in chunks of KBJ accumulators (FP64).
+constexpr int KBJ = 8;
+template <int G>
+__global__ void __launch_bounds__(VT)
+k_kb_gather(const int* __restrict__ rp, const int2* __restrict__ ent, long long rp_stride, long long ent_stride,
+            TurnArgs turns, const float2* __restrict__ y, float2* __restrict__ grid, int J, int S) {
+  constexpr int GG = G * G;
+  const int p = blockIdx.x * VT + threadIdx.x, b = blockIdx.y;
+  if (p >= GG) return;
+  const int t = turns.t[b];
+  const int* r = rp + t * rp_stride;
+  const int2* e = ent + t * ent_stride;
+  const int e0 = r[p], e1 = r[p + 1];
+  for (int j0 = 0; j0 < J; j0 += KBJ) {
+    double2 acc[KBJ];
+#pragma unroll
+    for (int q = 0; q < KBJ; ++q) acc[q] = make_double2(0.0, 0.0);
+    const int nj = J - j0 < KBJ ? J - j0 : KBJ;
+    for (int k = e0; k < e1; ++k) {
+      const int2 en = e[k];
+      const double wv = (double)__int_as_float(en.y);
+      const float2* ys = y + ((size_t)b * J + j0) * S + en.x;
+#pragma unroll
+      for (int q = 0; q < KBJ; ++q) {
+        if (q < nj) {
+          const float2 v = ys[(size_t)q * S];
+          acc[q].x += wv * v.x;
+          acc[q].y += wv * v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KBJ; ++q)
+      if (q < nj) grid[((size_t)b * J + j0 + q) * GG + p] = make_float2((float)acc[q].x, (float)acc[q].y);
+  }
+}
+
+// Inverse FFT of grid rows (all G samples) keeping the R image columns.
+template <int G, class S2>
+__global__ void __launch_bounds__(row_threads<G>())
+k_kb_rows(const float2* __restrict__ grid, S2* __restrict__ out, const double2* __restrict__ tw, int nlines) {
+  using T = Team<G>;
+  constexpr int R = G / 2, RT = row_lines<G>();
+  __shared__ C lds[RT * T::LDSN];
+  const int rl0 = (int)threadIdx.x / T::SIZE;
+  const int row0 = blockIdx.x * RT + rl0;
+  const bool act = rl0 < RT && row0 < nlines;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
+  const int row = act ? row0 : 0;
+  const float2* line = grid + (size_t)row * G;
+  C v[T::G1];
+  fsA<G, +1, SET_ALL, SET_IMG>(tl, lds + rl * T::LDSN, tw, [&](int n) -> C { return to_d(line[n]); }, v);
+  if (tl < T::G2) {
+    S2* o = out + (size_t)row * R;
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+        const int ix = img_idx<G>(T::G2 * k1 + tl);
+        if (ix >= 0) o[ix] = store_as<S2>(v[k1]);
+      }
+    });
+  }
+}
+
+// Inverse FFT of the columns of the row output keeping R rows; deapodisation.
+template <int G, class S2>
+__global__ void __launch_bounds__(cols_threads<G>())
+k_kb_cols(const S2* __restrict__ in, const float* __restrict__ cinv, const double2* __restrict__ tw,
+          float2* __restrict__ z) {
+  using T = Team<G>;
+  constexpr int R = G / 2, NT = R / TW;
+  __shared__ C lds[TW * T::LDSC];
+  const bool act = (int)threadIdx.x < TW * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT;
+  const int x = tile * TW + col;
+  const S2* c0 = in + (size_t)bj * G * R + x;
+  C v[T::G1];
+  fsA<G, +1, SET_ALL, SET_IMG>(tl, lds + col * T::LDSC, tw, [&](int n) -> C { return to_d(c0[(size_t)n * R]); }, v);
+  if (tl < T::G2) {
+    const double cx = cinv[x];
+    float2* o = z + (size_t)bj * R * R + x;
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+        const int iy = img_idx<G>(T::G2 * k1 + tl);
+        if (iy >= 0) o[(size_t)iy * R] = to_f(cscale(v[k1], cx * (double)cinv[iy]));
+      }
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-grid launch table
 // ---------------------------------------------------------------------------
 
@@ -630,13 +730,32 @@ struct GLaunch {
     k_fft_cols_psf<G><<<G / TW, TH_COLS, 0, st>>>(w.psf, P, w.tw, scale);
     return hipGetLastError();
   }
+  template <class S2>
+  static hipError_t kb_grid_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns,
+                              const float2* y, float2* z) {
+    constexpr int RT = row_lines<G>();
+    dim3 g1((G * G + VT - 1) / VT, s.B);
+    k_kb_gather<G><<<g1, VT, 0, st>>>(w.kbr, w.kbe, (long long)G * G + 1, s.kbe_stride, turns, y, w.KG, s.J, s.S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nlines = s.B * s.J * G;
+    k_kb_rows<G, S2><<<(nlines + RT - 1) / RT, TH_ROW1, 0, st>>>(w.KG, static_cast<S2*>(w.U2), w.tw, nlines);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_kb_cols<G, S2><<<s.B * s.J * s.NT, TH_COLS, 0, st>>>(static_cast<const S2*>(w.U2), w.kbc, w.tw, z);
+    return hipGetLastError();
+  }
+  static hipError_t kb_grid(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns,
+                            const float2* y, float2* z) {
+    return s.fast ? kb_grid_t<float2>(s, w, st, turns, y, z) : kb_grid_t<double2>(s, w, st, turns, y, z);
+  }
 };
 
 template <int G>
 constexpr GTable make_table() {
   return GTable{&GLaunch<G>::coil_rows, &GLaunch<G>::coil_rows_cg, &GLaunch<G>::cols_fwd,
                 &GLaunch<G>::toep_rows, &GLaunch<G>::cols_back, &GLaunch<G>::coilh_rows,
-                &GLaunch<G>::psf_fft, row_lines<G>()};
+                &GLaunch<G>::psf_fft, &GLaunch<G>::kb_grid, row_lines<G>()};
 }
 
 }  // namespace nlv
