@@ -36,6 +36,7 @@ struct nlinv_plan_s {
   hipStream_t cap_stream = nullptr;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graph_cache;
   float2* xb = nullptr;   // [B][X] source frames of nlinv_reconstruct_frames
+  std::vector<int2> kbn_host;   // per turn: grid points with short / long gridding rows
 };
 
 namespace {
@@ -142,7 +143,7 @@ void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBC, KG, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -193,7 +194,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   // Kaiser-Bessel gridding tables: (W + 1)^2 entries per sample and turn; left
   // out (exact gridding only) when they would take more than 2 GiB
   S.kbe_stride = (long long)S.S * KB_TAPS * KB_TAPS;
-  const double kb_bytes = (double)S.U * ((double)G * G + 1 + 2.0 * S.kbe_stride) * 4.0 +
+  const double kb_bytes = (double)S.U * (2.0 * G * G + 3 + 2.0 * S.kbe_stride) * 4.0 +
                           (double)S.B * S.J * G * G * 8.0;
   S.kb = (p->flags & NLINV_F_EXACT_GRID) == 0 && kb_bytes <= 2147483648.0;
 
@@ -233,6 +234,8 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->XB = take(B * X * c8);
   L->KBR = take(S.kb ? (size_t)S.U * ((size_t)Gs * Gs + 1) * 4 : 0);
   L->KBE = take(S.kb ? (size_t)S.U * (size_t)S.kbe_stride * 8 : 0);
+  L->KBP = take(S.kb ? (size_t)S.U * Gs * Gs * 4 : 0);
+  L->KBN = take(S.kb ? (size_t)S.U * 8 : 0);
   L->KBC = take(S.kb ? R * 4 : 0);
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
   L->total = off;
@@ -323,6 +326,20 @@ int build_turn(nlinv_plan plan, const float* d_traj, int turn) {
     std::vector<int2> ent;
     kb_table(traj.data(), s.S, s.G, rp, ent);
     if ((long long)ent.size() > s.kbe_stride) return fail(plan, NLINV_E_SIZE, "gridding table overflow");
+    // grid points by row length: short rows (one thread each) from the front,
+    // long rows (one wavefront each) from the back
+    const int GG = s.G * s.G;
+    std::vector<int> pts(GG);
+    int ns = 0, nl = 0;
+    for (int p = 0; p < GG; ++p) {
+      if (rp[p + 1] - rp[p] <= nlv::KB_SHORT) pts[ns++] = p;
+      else pts[GG - 1 - nl++] = p;
+    }
+    plan->kbn_host[turn] = make_int2(ns, nl);
+    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbp + (size_t)turn * GG, pts.data(), pts.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, plan->stream));
+    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbn + turn, &plan->kbn_host[turn], sizeof(int2), hipMemcpyHostToDevice,
+                                 plan->stream));
     NLV_HIP(plan, hipMemcpyAsync(plan->w.kbr + (size_t)turn * ((size_t)s.G * s.G + 1), rp.data(),
                                  rp.size() * sizeof(int), hipMemcpyHostToDevice, plan->stream));
     NLV_HIP(plan, hipMemcpyAsync(plan->w.kbe + (size_t)turn * s.kbe_stride, ent.data(), ent.size() * sizeof(int2),
@@ -440,6 +457,10 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   plan->xb = reinterpret_cast<float2*>(base + L.XB);
   w.kbr = reinterpret_cast<int*>(base + L.KBR);
   w.kbe = reinterpret_cast<int2*>(base + L.KBE);
+  w.kbp = reinterpret_cast<int*>(base + L.KBP);
+  w.kbn = reinterpret_cast<int2*>(base + L.KBN);
+  plan->kbn_host.assign(s.U, make_int2(0, 0));
+  w.kbn_host = plan->kbn_host.data();
   w.kbc = reinterpret_cast<float*>(base + L.KBC);
   w.KG = reinterpret_cast<float2*>(base + L.KG);
 

@@ -12,6 +12,7 @@ constexpr int TW = 8;         // columns per block in the column (y) passes (8 x
 constexpr int CHUNK = 512;    // vector elements per block in the CG kernels
 constexpr int VT = 256;       // threads per block in the vector / NUDFT kernels
 constexpr int MAXB = 64;      // largest batch (turn table passed by value)
+constexpr int KB_SHORT = 16;  // gridding rows up to this length take one thread
 
 struct TurnArgs { int32_t t[MAXB]; };
 
@@ -62,6 +63,9 @@ struct Bufs {
   double* rr[2];  // [B][stride] ping-pong
   int* kbr;       // [U][G*G+1] gridding table row starts (per grid point)
   int2* kbe;      // [U][kbe_stride] (sample index, weight bits) per table entry
+  int* kbp;       // [U][G*G] grid points: short rows from the front, long rows from the back
+  int2* kbn;      // [U] (short, long) point counts (device)
+  const int2* kbn_host;  // the same counts on the host (launch sizes)
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
 };
