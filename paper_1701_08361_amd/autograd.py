@@ -1,0 +1,83 @@
+"""torch.autograd form of the NLINV operators (Sec. 2.2).
+
+F_hat(x) = F(rho . W^-1 c_hat_j), its derivative DF_x(dx) and the adjoint
+DF_x^H(dy) as differentiable functions whose backward passes are the
+hand-written adjoints of the C-ABI (nlinv_apply_DF / nlinv_apply_DFH).  No
+arithmetic happens here: every forward and backward step is one library call.
+
+The gradient rules follow from two facts of the model:
+  * F_hat is bilinear in (rho, c_hat) with no conjugation, so for a real loss
+    the gradient through y = F_hat(x) is DF_x^H(g);
+  * DF_x(dx) is symmetric in its two arguments, DF_x(dx) = DF_dx(x), so its
+    gradient with respect to x is DF_dx^H(g), and by the adjoint identity the
+    gradient of DF_x^H(dy) with respect to x is DF_g^H(dy).
+Gradients use PyTorch's convention for complex tensors: for a real loss L,
+dL = Re<grad, dx>.
+
+`ops` is any object with apply_F / apply_DF / apply_DFH(traj, xhat, ...) in
+the shapes of paper_1701_08361_amd.nlinv.Plan (xhat [B][X], data [B][J][S]).
+"""
+from __future__ import annotations
+
+import torch
+
+
+class _F(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xhat, ops, traj):
+        ctx.ops, ctx.traj = ops, traj
+        ctx.save_for_backward(xhat)
+        return ops.apply_F(traj, xhat.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        (xhat,) = ctx.saved_tensors
+        gx = ctx.ops.apply_DFH(ctx.traj, xhat.contiguous(), g.contiguous()) if ctx.needs_input_grad[0] else None
+        return gx, None, None
+
+
+class _DF(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xhat, dx, ops, traj):
+        ctx.ops, ctx.traj = ops, traj
+        ctx.save_for_backward(xhat, dx)
+        return ops.apply_DF(traj, xhat.contiguous(), dx.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        xhat, dx = ctx.saved_tensors
+        g = g.contiguous()
+        gx = ctx.ops.apply_DFH(ctx.traj, dx.contiguous(), g) if ctx.needs_input_grad[0] else None
+        gdx = ctx.ops.apply_DFH(ctx.traj, xhat.contiguous(), g) if ctx.needs_input_grad[1] else None
+        return gx, gdx, None, None
+
+
+class _DFH(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xhat, dy, ops, traj):
+        ctx.ops, ctx.traj = ops, traj
+        ctx.save_for_backward(xhat, dy)
+        return ops.apply_DFH(traj, xhat.contiguous(), dy.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        xhat, dy = ctx.saved_tensors
+        g = g.contiguous()
+        gx = ctx.ops.apply_DFH(ctx.traj, g, dy.contiguous()) if ctx.needs_input_grad[0] else None
+        gdy = ctx.ops.apply_DF(ctx.traj, xhat.contiguous(), g) if ctx.needs_input_grad[1] else None
+        return gx, gdy, None, None
+
+
+def F(ops, traj, xhat):
+    """y = F_hat(xhat) [B][J][S], differentiable in xhat."""
+    return _F.apply(xhat, ops, traj)
+
+
+def DF(ops, traj, xhat, dx):
+    """DF_xhat(dx) [B][J][S], differentiable in xhat and dx."""
+    return _DF.apply(xhat, dx, ops, traj)
+
+
+def DFH(ops, traj, xhat, dy):
+    """DF_xhat^H(dy) [B][X], differentiable in xhat and dy."""
+    return _DFH.apply(xhat, dy, ops, traj)

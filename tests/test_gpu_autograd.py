@@ -1,0 +1,113 @@
+"""Differentiation through the HIP operators (paper_1701_08361_amd.autograd):
+gradients of least-squares losses through F_hat, DF and DF^H on the GPU
+against the FP64 oracle's closed forms, and against central finite
+differences of the GPU forward pass."""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1701_08361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1701_08361_amd import nlinv
+    nlinv.load()            # fails loudly when the HIP library is missing
+    return _t
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _case(torch, N=32, J=4, K=7, seed=31):
+    from paper_1701_08361_amd import nlinv
+    print(f"[case] autograd N={N} J={J} K={K} seed={seed}", flush=True)
+    plan = nlinv.Plan(N, J, K)
+    g = O.Geometry.make(N, J)
+    traj = synth.radial_trajectory(N, K, 2 * N, 0, 1)
+    x = synth.random_xhat(seed, g.R, J, g.Gc, 1.0, 0.3)
+    dx = synth.random_xhat(seed + 1, g.R, J, g.Gc, 1.0, 0.3)
+    y = synth.random_samples(seed + 2, J, K * 2 * N)
+    tt = torch.from_numpy(traj[None].copy()).cuda()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a[None])).cuda()
+    return plan, g, traj, tt, x, dx, y, dev
+
+
+def test_grad_F_matches_oracle(torch):
+    from paper_1701_08361_amd import autograd as AG
+    plan, g, traj, tt, x, dx, y, dev = _case(torch)
+    xt = dev(x).requires_grad_(True)
+    loss = (AG.F(plan, tt, xt) - dev(y)).abs().pow(2).sum()
+    loss.backward()
+    r = O.F_hat(g, x.astype(np.complex128), traj).reshape(g.J, -1) - y
+    ref = 2 * O.DFH_hat(g, x.astype(np.complex128), r, traj)
+    e = rel(xt.grad.cpu().numpy()[0], ref)
+    print(f"grad F rel {e:.2e}")
+    assert e < GRAD_TOL
+
+
+def test_grad_DF_matches_oracle(torch):
+    from paper_1701_08361_amd import autograd as AG
+    plan, g, traj, tt, x, dx, y, dev = _case(torch, seed=41)
+    xt, dt = dev(x).requires_grad_(True), dev(dx).requires_grad_(True)
+    loss = (AG.DF(plan, tt, xt, dt) - dev(y)).abs().pow(2).sum()
+    loss.backward()
+    xd, dd = x.astype(np.complex128), dx.astype(np.complex128)
+    r = O.DF_hat(g, xd, dd, traj).reshape(g.J, -1) - y
+    ex = rel(xt.grad.cpu().numpy()[0], 2 * O.DFH_hat(g, dd, r, traj))
+    ed = rel(dt.grad.cpu().numpy()[0], 2 * O.DFH_hat(g, xd, r, traj))
+    print(f"grad DF: x rel {ex:.2e}, dx rel {ed:.2e}")
+    assert ex < GRAD_TOL and ed < GRAD_TOL
+
+
+def test_grad_DFH_matches_oracle(torch):
+    from paper_1701_08361_amd import autograd as AG
+    plan, g, traj, tt, x, dx, y, dev = _case(torch, seed=51)
+    xt, vt = dev(x).requires_grad_(True), dev(y).requires_grad_(True)
+    w = dx
+    loss = (AG.DFH(plan, tt, xt, vt) - dev(w)).abs().pow(2).sum()
+    loss.backward()
+    xd = x.astype(np.complex128)
+    r = O.DFH_hat(g, xd, y, traj) - w
+    ex = rel(xt.grad.cpu().numpy()[0], 2 * O.DFH_hat(g, r, y, traj))
+    ev = rel(vt.grad.cpu().numpy()[0], 2 * O.DF_hat(g, xd, r, traj).reshape(g.J, -1))
+    print(f"grad DFH: x rel {ex:.2e}, dy rel {ev:.2e}")
+    assert ex < GRAD_TOL and ev < GRAD_TOL
+
+
+def test_grad_F_finite_differences(torch):
+    """Central differences of the float32 GPU loss agree with Re<grad, u>, for
+    the gradient direction and two random directions.  The data are half the
+    model output plus noise, so the loss is small against its slope and the
+    float32 rounding of the loss stays far below the slope x step."""
+    from paper_1701_08361_amd import autograd as AG
+    plan, g, traj, tt, x, dx, y, dev = _case(torch, seed=61)
+    ydata = (0.5 * O.F_hat(g, x.astype(np.complex128), traj).reshape(g.J, -1) + 0.01 * y).astype(np.complex64)
+    xt = dev(x).requires_grad_(True)
+    yt = dev(ydata)
+    loss_of = lambda v: float((AG.F(plan, tt, v) - yt).abs().pow(2).sum())
+    loss = (AG.F(plan, tt, xt) - yt).abs().pow(2).sum()
+    loss.backward()
+    grad = xt.grad.detach()
+    scale = float(grad.abs().pow(2).sum().sqrt()) * float(np.linalg.norm(x))
+    rng = np.random.default_rng(7)
+    dirs = [grad / grad.abs().pow(2).sum().sqrt() * float(np.linalg.norm(x))]
+    for k in range(2):
+        u = rng.standard_normal(g.X) + 1j * rng.standard_normal(g.X)
+        dirs.append(torch.from_numpy((u / np.linalg.norm(u) * np.linalg.norm(x)).astype(np.complex64)[None]).cuda())
+    eps = 1e-3
+    for k, u in enumerate(dirs):
+        with torch.no_grad():
+            fd = (loss_of(xt + eps * u) - loss_of(xt - eps * u)) / (2 * eps)
+        an = float((grad.conj() * u).real.sum())
+        print(f"direction {k}: finite difference {fd:.6e}, gradient {an:.6e}")
+        assert abs(fd - an) <= 1e-3 * scale
