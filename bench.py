@@ -68,12 +68,17 @@ def measured_traffic(kind: str):
     return out
 
 
+# Mixed sizes: (N, J, K, series) per shape, 16 series in all
+MIXED = [(128, 8, 11, 5), (160, 10, 15, 6), (192, 16, 21, 5)]
+
+
 def _series(args):
-    seed, frames, threads = args
+    seed, frames, threads = args[:3]
+    n, j, k = args[3:] if len(args) > 3 else (N, J, K)
     from threadpoolctl import threadpool_limits
     from paper_1701_08361_amd import synth
     with threadpool_limits(threads):
-        s = synth.real_time_series(seed=seed, N=N, J=J, J_phys=J_PHYS, K=K, U=U, frames=frames)
+        s = synth.real_time_series(seed=seed, N=n, J=j, J_phys=max(J_PHYS, 2 * j), K=k, U=U, frames=frames)
     return s.traj, s.y, s.turn
 
 
@@ -294,6 +299,49 @@ def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs):
     return lat, S * periods, wall
 
 
+def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
+    """Series of several shapes advanced together, one batched plan per shape:
+    one after another on one stream, or each on its own HIP stream so that
+    their kernels overlap.  groups: [(N, J, K, data)].  Returns per-step ms."""
+    runs = []
+    for (n, j, k, data) in groups:
+        B = len(data)
+        plan = nl.Plan(n, j, k, U=U, batch=B, newton=M, cg=C)
+        plan.set_graphs(graphs)
+        traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()
+        y = torch.from_numpy(np.stack([d[1] for d in data], axis=1)).cuda()
+        for t in range(U):
+            plan.psf(traj[t, 0].contiguous(), t)
+        st = torch.cuda.Stream() if concurrent else torch.cuda.current_stream()
+        xs = [torch.empty(B, plan.X, dtype=torch.complex64, device="cuda") for _ in range(2)]
+        z = torch.empty(B, j, n, n, dtype=torch.complex64, device="cuda")
+        img = torch.empty(B, n, n, dtype=torch.float32, device="cuda")
+        runs.append(dict(plan=plan, traj=traj, y=y, turn=data[0][2], st=st, xs=xs, z=z, img=img, B=B))
+    torch.cuda.synchronize()
+
+    def step(i):
+        for r in runs:
+            f = i % r["traj"].shape[0]
+            tn = [int(r["turn"][f])] * r["B"]
+            with torch.cuda.stream(r["st"]):
+                r["plan"].grid(r["traj"][f], r["y"][f], turns=tn, z=r["z"])
+                prev = None if i == 0 else r["xs"][(i - 1) & 1]
+                r["plan"].reconstruct(r["z"], tn, xprev=prev, xhat=r["xs"][i & 1], init=1 if i == 0 else 2,
+                                      img=r["img"])
+        torch.cuda.synchronize()
+
+    for i in range(warmup):
+        step(i)
+    per = []
+    for i in range(warmup, warmup + steps):
+        t0 = time.perf_counter()
+        step(i)
+        per.append((time.perf_counter() - t0) * 1e3)
+    for r in runs:
+        r["plan"].close()
+    return per
+
+
 def pct(v, q):
     v = sorted(v)
     k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
@@ -345,6 +393,8 @@ def main():
     ap.add_argument("--serve-slices", type=int, default=4, help="slices streamed in the serving run (0 = skip)")
     ap.add_argument("--serve-periods", type=int, default=60, help="timed frame periods per slice")
     ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
+    ap.add_argument("--mixed-steps", type=int, default=10,
+                    help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -361,6 +411,23 @@ def main():
     plain_data = make_data([2], frames_plain, 1) if args.mode != "batched" else None
     batch_data = (make_data(list(range(2, 2 + args.batch)), frames_batch, args.workers)
                   if args.mode != "plain" else None)
+    mixed_data = None
+    if args.mixed_steps > 0 and args.mode == "both" and not args.fast:
+        frames_mixed = max(U, 2 * U + args.mixed_steps)
+        seeds, jobs = 100, []
+        for (n, j, k, ns) in MIXED:
+            jobs.append([(seeds + q, frames_mixed, 1, n, j, k) for q in range(ns)])
+            seeds += ns
+        flat = [a for g in jobs for a in g]
+        if args.workers > 1:
+            with mp.get_context("fork").Pool(min(args.workers, len(flat))) as pool:
+                res = pool.map(_series, flat)
+        else:
+            res = [_series(a) for a in flat]
+        mixed_data, q = [], 0
+        for (n, j, k, ns) in MIXED:
+            mixed_data.append((n, j, k, res[q:q + ns]))
+            q += ns
     t_gen = time.perf_counter() - t_gen
 
     cpu = None if args.no_cpu else cpu_baseline()
@@ -440,6 +507,15 @@ def main():
             serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
+    if mixed_data is not None:
+        nfr = sum(len(g[3]) for g in mixed_data)
+        mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],
+                 "frames_per_step": nfr}
+        for name, conc in (("one_stream", False), ("streams", True)):
+            per = run_mixed(torch, nl, mixed_data, args.mixed_steps, 2 * U, conc, not args.no_graphs)
+            mixed[name] = {"fps": nfr / (sum(per) / len(per) / 1e3), "ms_per_step": {"p50": pct(per, 50),
+                                                                                    "p99": pct(per, 99)}}
+        out["mixed"] = mixed
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
                      "plain_batch": 1, "batched_batch": args.batch, "fast_grid": bool(args.fast),

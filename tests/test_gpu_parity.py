@@ -186,6 +186,28 @@ def test_reconstruct_single_frame_c1(torch):
     assert e_img < IMG_TOL and e_rc < IMG_TOL
 
 
+@pytest.mark.parametrize("N,J,K,M,C", [
+    (128, 8, 11, 4, 8),     # smallest mixed-size configuration (256 grid)
+    (192, 16, 21, 3, 6),    # largest mixed-size configuration (384 grid, 16 coils, 21 spokes)
+    (224, 16, 21, 2, 4),    # largest supported grid (448), 16 coils
+    (32, 1, 1, 3, 4),       # degenerate: one coil, one spoke
+])
+def test_reconstruct_sizes(torch, N, J, K, M, C):
+    """Single frames across the supported grid sizes and the degenerate case,
+    Kaiser-Bessel gridding included, against the oracle."""
+    print_case("recon sizes", N=N, J=J, K=K, M=M, C=C)
+    s = synth.single_frame(seed=3, N=N, J=J, K=K)
+    plan = nl().Plan(N, J, K, newton=M, cg=C)
+    z = plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0])
+    x, img, _ = plan.reconstruct(z, [0], want_img=True)
+    g = O.Geometry.make(N, J)
+    P = O.psf_kernel(s.traj[0], g.R, g.G)
+    xr = O.reconstruct(g, O.grid(s.y[0], s.traj[0], g.R), P, newton=M, cg_iters=C)
+    e_img, e_rc = _recon_compare(g, host(x)[0], host(img)[0], xr)
+    print(f"sizes N={N} J={J} K={K}: image rel {e_img:.2e}  rho*c rel {e_rc:.2e}")
+    assert e_img < IMG_TOL and e_rc < IMG_TOL
+
+
 def test_reconstruct_batched_series_with_prev(torch):
     """Batch of 3 frames from 3 turns, each regularised to (and started from) a
     different previous estimate; ragged sizes (J=5, K=7) on a 64-px grid."""
