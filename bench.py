@@ -79,7 +79,9 @@ def _series(args):
     from paper_1701_08361_amd import synth
     with threadpool_limits(threads):
         s = synth.real_time_series(seed=seed, N=n, J=j, J_phys=max(J_PHYS, 2 * j), K=k, U=U, frames=frames)
-    return s.traj, s.y, s.turn
+    # the phantom's combined image of frame 0 (target of the differentiation run)
+    target = s.truth[0] * np.linalg.norm(s.coils.reshape(j, -1), axis=0).reshape(n, n) * s.scale
+    return s.traj, s.y, s.turn, target
 
 
 def make_data(seeds, frames, workers):
@@ -342,6 +344,37 @@ def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
     return per
 
 
+def run_diff(torch, nl, data, steps, newton, cg):
+    """Unrolled, checkpointed IRGNM of frame 0 (batch 1) with the loss
+    ||image - phantom||^2 and its gradient with respect to the data and alpha_0.
+    Returns (forward ms, forward + backward ms) per step and the gradient norms."""
+    from paper_1701_08361_amd import unrolled as UR
+    plan = nl.Plan(N, J, K, U=U)
+    traj = torch.from_numpy(data[0][0][0:1]).cuda()
+    y0 = torch.from_numpy(data[0][1][0:1]).cuda()
+    target = torch.from_numpy(data[0][3]).cuda().float()
+    fwd, tot = [], []
+    gy = ga = None
+    for i in range(steps + 1):
+        y = y0.clone().requires_grad_(True)
+        a0 = torch.tensor(1.0, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = UR.reconstruct(plan, traj, y, N, newton=newton, cg_iters=cg, alpha0=a0)
+        loss = ((UR.image(plan, x, N)[0] - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if i > 0:                       # the first pass is a warm-up
+            fwd.append((t1 - t0) * 1e3)
+            tot.append((t2 - t0) * 1e3)
+        gy, ga = float(y.grad.abs().pow(2).sum().sqrt()), float(a0.grad)
+    plan.close()
+    return fwd, tot, gy, ga
+
+
 def pct(v, q):
     v = sorted(v)
     k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
@@ -393,6 +426,8 @@ def main():
     ap.add_argument("--serve-slices", type=int, default=4, help="slices streamed in the serving run (0 = skip)")
     ap.add_argument("--serve-periods", type=int, default=60, help="timed frame periods per slice")
     ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
+    ap.add_argument("--diff-steps", type=int, default=2,
+                    help="timed forward + backward passes of the unrolled 5 x 20 reconstruction (0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
     args = ap.parse_args()
@@ -507,6 +542,13 @@ def main():
             serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
+    if plain_data is not None and args.diff_steps > 0 and not args.fast:
+        fwd, tot, gy, ga = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
+        out["differentiation"] = {
+            "form": "unrolled IRGNM, 5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
+                    "loss ||image - phantom||^2; gradients w.r.t. the data and alpha_0",
+            "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50),
+            "grad_norm_data": gy, "grad_alpha0": ga}
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],

@@ -202,6 +202,12 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
                        double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
 
+/* Adjoint of the coil synthesis c_j = W^-1 c_hat_j (Sec. 2.2, Sec. 3.2):
+ * d_xhat [B][X] gets the image block 0 and the coil blocks
+ * W^-H c_j = D_W^-1 crop_{G_c} F_u pad_G c_j of d_coils [B][J][R][R].
+ * Used as the backward pass of nlinv_coils in the differentiation form. */
+int nlinv_apply_WH(nlinv_plan plan, const nlinv_c64* d_coils, nlinv_c64* d_xhat);
+
 /* Coil images c_j = W^-1 c_hat_j [B][J][R][R] and/or the combined image
  * |rho| sqrt(sum_j |c_j|^2) [B][R][R] of d_xhat; either output may be NULL. */
 int nlinv_coils(nlinv_plan plan, const nlinv_c64* d_xhat, nlinv_c64* d_coils, float* d_img);

@@ -14,8 +14,10 @@ The gradient rules follow from two facts of the model:
 Gradients use PyTorch's convention for complex tensors: for a real loss L,
 dL = Re<grad, dx>.
 
-`ops` is any object with apply_F / apply_DF / apply_DFH(traj, xhat, ...) in
-the shapes of paper_1701_08361_amd.nlinv.Plan (xhat [B][X], data [B][J][S]).
+`ops` is any object with apply_F / apply_DF / apply_DFH(traj, xhat, ...),
+coils(xhat, want_img=False) and apply_WH(coils) in the shapes of
+paper_1701_08361_amd.nlinv.Plan (xhat [B][X], data [B][J][S], coil images
+[B][J][R][R]).
 """
 from __future__ import annotations
 
@@ -66,6 +68,23 @@ class _DFH(torch.autograd.Function):
         gx = ctx.ops.apply_DFH(ctx.traj, g, dy.contiguous()) if ctx.needs_input_grad[0] else None
         gdy = ctx.ops.apply_DF(ctx.traj, xhat.contiguous(), g) if ctx.needs_input_grad[1] else None
         return gx, gdy, None, None
+
+
+class _Coils(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xhat, ops):
+        ctx.ops = ops
+        c, _ = ops.coils(xhat.contiguous(), want_img=False)
+        return c
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.ops.apply_WH(g.contiguous()), None
+
+
+def coils(ops, xhat):
+    """Coil images c_j = W^-1 c_hat_j [B][J][R][R] (linear in the coil block)."""
+    return _Coils.apply(xhat, ops)
 
 
 def F(ops, traj, xhat):

@@ -822,6 +822,19 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
   return NLINV_OK;
 }
 
+int nlinv_apply_WH(nlinv_plan plan, const nlinv_c64* d_coils, nlinv_c64* d_xhat) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_coils, "d_coils"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const void* c = d_coils;
+  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 3, c, nullptr, nullptr, nullptr, nullptr, 0.0));
+  NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, nullptr, nullptr, 0.0, w.Q, nullptr));
+  NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, reinterpret_cast<float2*>(d_xhat), false));
+  return NLINV_OK;
+}
+
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat, double alpha,
                        const nlinv_c64* d_p, nlinv_c64* d_q) {
   NLV_CHECK(check_plan(plan));

@@ -86,7 +86,8 @@ struct GTable {
   // row pass: FFT, multiply by the PSF kernel of each item's turn, inverse FFT (in place on U2)
   hipError_t (*toep_rows)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns);
   // column pass back: mode 0 normal (dot partials to pq), 1 residual (z - T u), 2 adjoint of an
-  // image-space float32 input.  Writes PR and U1 (as the W^-H column stage).
+  // image-space float32 input, 3 plain W^-H column stage of coil images.  Writes U1 (as the
+  // W^-H column stage) and, except in mode 3, PR.
   hipError_t (*cols_back)(const Shape&, const Bufs&, hipStream_t, int mode, const void* in,
                           const float2* co, const float2* xh, const float2* z, const double2* pv,
                           double alpha);
@@ -112,9 +113,10 @@ hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const f
                           const float2* xprev, double alpha);
 hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
                             const double2* p, Partials rr, float2* xh, double alpha);
-// out (float32 [B][X]) = (sum_j PR_j + alpha p ; Q) ; p may be null
+// out (float32 [B][X]) = (sum_j PR_j + alpha p ; Q) ; p may be null; without the image
+// block (image_block false) the image part is alpha p, or zero when p is null
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
-                           double alpha, float2* out);
+                           double alpha, float2* out, bool image_block = true);
 hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const float2* src);
 // mode 1: (rho = 1, c = 0); 2: copy xprev [B][X]; 3: broadcast xprev [X] to every item
 hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);

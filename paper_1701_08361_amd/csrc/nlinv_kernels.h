@@ -344,7 +344,8 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
 
 // ---------------------------------------------------------------------------
 // cols_back: iFFT along y (or an image-space input), channel terms, FFT along y
-// to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32).
+// to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32),
+// 3 plain W^-H column stage of coil images `in` (no channel products, no rho).
 // ---------------------------------------------------------------------------
 template <int G, int MODE, class S2>
 __global__ void __launch_bounds__(cols_threads<G>())
@@ -364,7 +365,7 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   const size_t img = (size_t)bj * R * R;
 
   C v[T::G1];
-  if constexpr (MODE != 2) {
+  if constexpr (MODE < 2) {
     const S2* c0 = static_cast<const S2*>(inp) + (size_t)bj * G * R + x;
     fsA<G, +1, SET_ALL, SET_IMG>(tl, L, tw, [&](int n) -> C { return to_d(c0[(size_t)n * R]); }, v);
   } else {
@@ -388,15 +389,19 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
       if (iy >= 0) {
         const size_t e = (size_t)iy * R + x;
         C t = v[k1];
-        if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
-        const float2 prf = to_f(cjmul(to_d(co[img + e]), t));
-        PR[img + e] = prf;
-        if constexpr (MODE == 0) {
-          const double2 dr = pv[(size_t)b * X + e];
-          dot += dr.x * prf.x + dr.y * prf.y;
-          if (j == 0) dot += alpha * (dr.x * dr.x + dr.y * dr.y);
+        if constexpr (MODE == 3) {
+          s = t;   // plain W^-H of a coil image: no channel products
+        } else {
+          if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
+          const float2 prf = to_f(cjmul(to_d(co[img + e]), t));
+          PR[img + e] = prf;
+          if constexpr (MODE == 0) {
+            const double2 dr = pv[(size_t)b * X + e];
+            dot += dr.x * prf.x + dr.y * prf.y;
+            if (j == 0) dot += alpha * (dr.x * dr.x + dr.y * dr.y);
+          }
+          s = cjmul(to_d(rho[e]), t);
         }
-        s = cjmul(to_d(rho[e]), t);
       }
       v[k1] = s;
     });
@@ -754,6 +759,7 @@ struct GLaunch {
       case 0: k_cols_back<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
       case 1: k_cols_back<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
       case 2: k_cols_back<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
+      case 3: k_cols_back<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -146,7 +146,7 @@ k_finalize(const float2* __restrict__ PR, const double2* __restrict__ p, double 
     const size_t ve = (size_t)b * X + e;
     if (e < RR) {
       double sx = 0.0, sy = 0.0;
-      for (int j = 0; j < J; ++j) {
+      for (int j = 0; PR && j < J; ++j) {   // PR == nullptr: image block zero
         const float2 pr = PR[((size_t)b * J + j) * RR + e];
         sx += pr.x;
         sy += pr.y;
@@ -429,8 +429,9 @@ hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int i
 }
 
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
-                           double alpha, float2* out) {
-  k_finalize<<<s.B * s.NCH, VT, 0, st>>>(w.PR, p, alpha, w.Q, out, s.J, s.R * s.R, s.X, s.NCH);
+                           double alpha, float2* out, bool image_block) {
+  k_finalize<<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J, s.R * s.R, s.X,
+                                         s.NCH);
   return hipGetLastError();
 }
 

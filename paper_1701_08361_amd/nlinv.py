@@ -65,6 +65,7 @@ def load() -> ctypes.CDLL:
         "nlinv_apply_DF": [_P, _P, _P, _P, _P],
         "nlinv_apply_DFH": [_P, _P, _P, _P, _P],
         "nlinv_apply_normal": [_P, _P, _P, ctypes.c_double, _P, _P],
+        "nlinv_apply_WH": [_P, _P, _P],
         "nlinv_coils": [_P, _P, _P, _P],
         "nlinv_sync": [_P],
         "nlinv_set_graphs": [_P, _I],
@@ -293,6 +294,16 @@ class Plan:
         _check(self.lib.nlinv_apply_DFH(self.handle, self._ptr(traj), self._ptr(xhat), self._ptr(dy),
                                         self._ptr(dx)), self.handle)
         return dx
+
+    def apply_WH(self, coils, xhat=None):
+        """Adjoint of the coil synthesis: image block 0, coil blocks W^-H c_j."""
+        torch = self.torch
+        self._t(coils, torch.complex64, (self.B, self.J, self.R, self.R), "coils")
+        xhat = self.empty(self.B, self.X) if xhat is None else xhat
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_WH(self.handle, self._ptr(coils), self._ptr(xhat)), self.handle)
+        return xhat
 
     def apply_normal(self, turns, xhat, p, alpha: float = 0.0, q=None):
         torch = self.torch

@@ -13,10 +13,21 @@ from paper_1701_08361_amd import synth
 
 
 class OracleOps:
-    """apply_F / apply_DF / apply_DFH in the shapes of the C-ABI binding, FP64."""
+    """apply_F / apply_DF / apply_DFH, coils and apply_WH in the shapes of the
+    C-ABI binding, FP64."""
 
     def __init__(self, g):
         self.g = g
+        self.X = g.X
+
+    def coils(self, xhat, want_img=False):
+        return self._each(lambda x: self.g.coils(x), xhat), None
+
+    def apply_WH(self, c):
+        g = self.g
+        def one(cj):
+            return g.pack(np.zeros((g.R, g.R)), O.winvh(cj, g.G, g.Gc, g.w))
+        return self._each(one, c)
 
     def _each(self, fn, *args):
         out = [fn(*[a[b].detach().numpy() for a in args]) for b in range(args[0].shape[0])]
@@ -74,3 +85,40 @@ def test_data_fidelity_gradient_is_the_gauss_newton_rhs():
     r = O.F_hat(g, x.detach().numpy()[0], traj.numpy()[0]).reshape(g.J, -1) - y.numpy()[0]
     ref = 2 * O.DFH_hat(g, x.detach().numpy()[0], r, traj.numpy()[0])
     assert np.allclose(x.grad.numpy()[0], ref, rtol=1e-10, atol=1e-10)
+
+
+def test_coils_gradcheck():
+    ops, traj, g, cx = _setup(seed=4)
+    x = cx(2, g.X).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x: AG.coils(ops, x), (x,), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_unrolled_equals_oracle_reconstruction():
+    """The unrolled form (operators F and F^H separately) reproduces the
+    oracle's IRGNM (normal operator through the PSF convolution): the same
+    iteration, since T = F^H F exactly."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _setup(B=1, N=8, J=2, K=5, seed=5)
+    s = synth.single_frame(seed=5, N=8, J=2, K=5)
+    t = s.traj.astype(np.float64)
+    y = torch.from_numpy(s.y.astype(np.complex128))
+    x = UR.reconstruct(ops, torch.from_numpy(t), y, g.R, newton=3, cg_iters=4, checkpoint_steps=True)
+    P = O.psf_kernel(t[0], g.R, g.G)
+    ref = O.reconstruct(g, O.grid(s.y[0].astype(np.complex128), t[0], g.R), P, newton=3, cg_iters=4)
+    err = np.linalg.norm(x.numpy()[0] - ref) / np.linalg.norm(ref)
+    assert err < 1e-9, err
+
+
+def test_unrolled_gradcheck_data_and_alpha():
+    """Finite-difference check of d image / d (y, alpha_0) through 2 Newton steps
+    of 2 CG iterations, each step checkpointed."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _setup(B=1, N=8, J=2, K=3, seed=6)
+    y = (0.3 * cx(1, g.J, traj.shape[1] * traj.shape[2])).requires_grad_(True)
+    a0 = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+
+    def fn(y, a0):
+        x = UR.reconstruct(ops, traj[:1], y, g.R, newton=2, cg_iters=2, alpha0=a0)
+        return UR.image(ops, x, g.R)
+
+    assert torch.autograd.gradcheck(fn, (y, a0), eps=1e-6, atol=1e-5, rtol=1e-4)

@@ -111,3 +111,80 @@ def test_grad_F_finite_differences(torch):
         an = float((grad.conj() * u).real.sum())
         print(f"direction {k}: finite difference {fd:.6e}, gradient {an:.6e}")
         assert abs(fd - an) <= 1e-3 * scale
+
+
+def test_coil_synthesis_adjoint(torch):
+    """nlinv_apply_WH against the oracle's W^-H, and <W^-1 c_hat, v> = <c_hat, W^-H v>."""
+    from paper_1701_08361_amd import nlinv
+    N, J = 64, 5
+    print(f"[case] W^-H N={N} J={J}", flush=True)
+    plan = nlinv.Plan(N, J, 5)
+    g = O.Geometry.make(N, J)
+    rng = np.random.default_rng(71)
+    v = (rng.standard_normal((J, N, N)) + 1j * rng.standard_normal((J, N, N))).astype(np.complex64)
+    out = plan.apply_WH(torch.from_numpy(v[None]).cuda()).cpu().numpy()[0]
+    ref = g.pack(np.zeros((g.R, g.R)), O.winvh(v.astype(np.complex128), g.G, g.Gc, g.w))
+    e = rel(out, ref)
+    x = synth.random_xhat(72, g.R, J, g.Gc, 1.0, 1.0)
+    c, _ = plan.coils(torch.from_numpy(x[None]).cuda(), want_img=False)
+    lhs = np.vdot(c.cpu().numpy()[0].astype(np.complex128), v)
+    rhs = np.vdot(x[g.R * g.R:].astype(np.complex128), out[g.R * g.R:].astype(np.complex128))
+    print(f"W^-H rel {e:.2e}, adjoint mismatch {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert e < GRAD_TOL and abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    assert np.all(out[:g.R * g.R] == 0)
+
+
+def _unrolled_case(torch, N=32, J=4, K=7, M=3, C=4):
+    from paper_1701_08361_amd import nlinv
+    s = synth.real_time_series(seed=73, N=N, J=J, J_phys=6, K=K, U=1, frames=1)
+    plan = nlinv.Plan(N, J, K, U=1)
+    g = O.Geometry.make(N, J)
+    return plan, g, s
+
+
+def test_unrolled_forward_matches_oracle(torch):
+    """The unrolled form on the GPU (float32 operators, float32 CG algebra)
+    against the oracle's IRGNM with the same counts."""
+    from paper_1701_08361_amd import unrolled as UR
+    N, J, K, M, C = 32, 4, 7, 3, 4
+    print(f"[case] unrolled forward N={N} J={J} K={K} M={M} C={C}", flush=True)
+    plan, g, s = _unrolled_case(torch, N, J, K, M, C)
+    traj = torch.from_numpy(s.traj).cuda()
+    y = torch.from_numpy(s.y).cuda()
+    with torch.no_grad():
+        x = UR.reconstruct(plan, traj, y, g.R, newton=M, cg_iters=C)
+        img = UR.image(plan, x, g.R)
+    P = O.psf_kernel(s.traj[0], g.R, g.G)
+    xr = O.reconstruct(g, O.grid(s.y[0], s.traj[0], g.R), P, newton=M, cg_iters=C)
+    e = rel(img.cpu().numpy()[0], O.image(g, xr))
+    print(f"unrolled image rel {e:.2e}")
+    assert e < 1e-3
+
+
+def test_unrolled_gradients_match_fp64(torch):
+    """Gradients of ||image - phantom||^2 with respect to the data and alpha_0
+    through 3 checkpointed Newton steps of 4 CG iterations: GPU (float32)
+    against the same unrolled procedure in float64 on the oracle."""
+    from paper_1701_08361_amd import unrolled as UR
+    from test_autograd_cpu import OracleOps
+    N, J, K, M, C = 32, 4, 7, 3, 4
+    print(f"[case] unrolled gradients N={N} J={J} K={K} M={M} C={C}", flush=True)
+    plan, g, s = _unrolled_case(torch, N, J, K, M, C)
+    truth = s.truth[0] * np.linalg.norm(s.coils.reshape(J, -1), axis=0).reshape(N, N)
+
+    def grads(ops, traj, y0, dev, cdt, rdt):
+        y = torch.from_numpy(y0).to(dev, cdt).requires_grad_(True)
+        a0 = torch.tensor(1.0, dtype=rdt, device=dev, requires_grad=True)
+        x = UR.reconstruct(ops, traj, y, g.R, newton=M, cg_iters=C, alpha0=a0)
+        img = UR.image(ops, x, g.R)
+        t = torch.from_numpy(truth).to(dev, rdt)
+        loss = ((img[0] - t / t.norm() * img[0].detach().norm()) ** 2).sum()
+        loss.backward()
+        return y.grad.cpu().numpy(), float(a0.grad), float(loss.detach())
+
+    gy, ga, L = grads(plan, torch.from_numpy(s.traj).cuda(), s.y, "cuda", torch.complex64, torch.float32)
+    ry, ra, Lr = grads(OracleOps(g), torch.from_numpy(s.traj.astype(np.float64)), s.y.astype(np.complex128),
+                       "cpu", torch.complex128, torch.float64)
+    ey, ea = rel(gy, ry), abs(ga - ra) / abs(ra)
+    print(f"loss {L:.6e} vs {Lr:.6e}; grad y rel {ey:.2e}; grad alpha0 {ga:.6e} vs {ra:.6e} (rel {ea:.2e})")
+    assert ey < 1e-2 and ea < 1e-2
