@@ -406,7 +406,8 @@ def cpu_baseline(seconds_hint: float = 30.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed frames per series (plain)")
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="timed frames of the plain series (the 100-frame series repeats; >= 1000 for p99)")
     ap.add_argument("--warmup", type=int, default=10,
                     help="untimed frames; >= 10 so every (turn, buffer) graph is captured before timing")
     ap.add_argument("--batch", type=int, default=16)
@@ -424,7 +425,9 @@ def main():
     ap.add_argument("--relaxed-o", type=int, default=3, help="frames per relaxed group (o); 0 = skip")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     ap.add_argument("--serve-slices", type=int, default=4, help="slices streamed in the serving run (0 = skip)")
-    ap.add_argument("--serve-periods", type=int, default=60, help="timed frame periods per slice")
+    ap.add_argument("--serve-periods", type=int, default=250, help="timed frame periods per slice")
+    ap.add_argument("--hbm-batch", type=int, default=32,
+                    help="batch of an extra run whose working set exceeds the 256 MB Infinity Cache (0 = skip)")
     ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
     ap.add_argument("--diff-steps", type=int, default=2,
                     help="timed forward + backward passes of the unrolled 5 x 20 reconstruction (0 = skip)")
@@ -533,6 +536,18 @@ def main():
         if plain_data is None:
             out.update({"value": out["batched"]["fps"], "steps": args.batch_steps, "warmup": args.warmup,
                         "ms_per_step": out["batched"]["ms_per_step"]})
+    if batch_data is not None and args.hbm_batch > 0:
+        # working set of ~1 GB: the Toeplitz pass cannot be served from the last-level cache
+        hb = args.hbm_batch
+        data_hb = [batch_data[i % len(batch_data)] for i in range(hb)]
+        _, total_hb, (tms_hb, tl_hb) = run_mode(torch, nl, data_hb, hb, 3, args.warmup, args.fast, args.kernel,
+                                                2, not args.no_graphs)
+        if tl_hb:
+            out["hbm_check"] = {"batch": hb, "fps": hb * 3 / (total_hb / 1e3), "kernel": args.kernel,
+                                "avg_launch_us": tms_hb / tl_hb * 1e3,
+                                "achieved": kernel_bytes(args.kernel, hb, args.fast, 1) / (tms_hb / tl_hb / 1e3) / 1e9,
+                                "peak": HBM_PEAK_GBS}
+            out["hbm_check"]["frac"] = out["hbm_check"]["achieved"] / HBM_PEAK_GBS
     if batch_data is not None and args.serve_slices > 0 and not args.fast:
         S = min(args.serve_slices, len(batch_data))
         serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods}
