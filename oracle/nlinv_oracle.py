@@ -431,3 +431,25 @@ def reconstruct_series(g: Geometry, zs, Ps, sources: list | None = None, newton:
             x = x + newton_step(g, x, frame(h[m]), zs[n], Ps[n], alpha, cg_iters)
         out.append(x)
     return out
+
+
+# ---------------------------------------------------------------------------
+# channel compression (Sec. 3.1, preprocessing, with its calibration phase)
+# ---------------------------------------------------------------------------
+
+def compression_matrix(y0: np.ndarray, J: int) -> np.ndarray:
+    """Compression transform [J, J_phys] from a calibration frame y0 [J_phys, S].
+    Reading (the paper names channel compression and its calibration phase but
+    no method): principal components; the rows are the conjugated eigenvectors
+    of the channel covariance y0 y0^H for its J largest eigenvalues, in
+    descending order (each row fixed only up to a phase)."""
+    y0 = np.asarray(y0, np.complex128)
+    cov = y0 @ y0.conj().T
+    w, V = np.linalg.eigh(cov)
+    order = np.argsort(w)[::-1][:J]
+    return V[:, order].conj().T
+
+
+def compress(cc: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Virtual channels y_v[j] = sum_p cc[j, p] y[p]: [J, J_phys] x [..., J_phys, S]."""
+    return np.asarray(cc, np.complex128) @ np.asarray(y, np.complex128)

@@ -272,10 +272,13 @@ def _series_moving(R: int, n: int) -> Ellipse:
 
 def real_time_series(seed: int = 2, N: int = 160, J: int = 10, J_phys: int = 30, K: int = 15,
                      S_r: Optional[int] = None, U: int = 5, frames: int = 100,
-                     sigma: float = 1e-3) -> Series:
+                     sigma: float = 1e-3, compress: bool = True) -> Series:
     """Real-time series: deforming-ellipse phantom, J_phys random smooth coil maps
     (ring-Gaussian envelope x random low-order Fourier series) PCA-compressed to J
-    virtual channels, K spokes per frame with U rotated turns."""
+    virtual channels, K spokes per frame with U rotated turns.
+    compress=False returns the J_phys receive channels instead (scaled by
+    100 / ||frame 0||, noise added; J is ignored): the input of a pipeline that
+    compresses the channels itself."""
     rng = np.random.default_rng(seed)
     S_r = 2 * N if S_r is None else S_r
     R = N
@@ -296,11 +299,14 @@ def real_time_series(seed: int = 2, N: int = 160, J: int = 10, J_phys: int = 30,
         y_all[n] = kspace(traj, ells, coef, Q, R, static_cache=cache,
                           static_key=int(turns[n]), n_static=3)
         truth[n] = ellipse_image(R, ells)
-    cc = pca_matrix(y_all[0], J)                       # calibration on frame 0
-    yv = np.einsum("vp,fps->fvs", cc, y_all, optimize=True)
+    if compress:
+        cc = pca_matrix(y_all[0], J)                   # calibration on frame 0
+        yv = np.einsum("vp,fps->fvs", cc, y_all, optimize=True)
+        coils = np.einsum("vp,pyx->vyx", cc, coil_images(coef, Q, R), optimize=True)
+    else:
+        J, yv, coils = J_phys, y_all, coil_images(coef, Q, R)
     scale = 100.0 / np.linalg.norm(yv[0])
     yv = add_noise(rng, yv * scale, sigma)
-    coils = np.einsum("vp,pyx->vyx", cc, coil_images(coef, Q, R), optimize=True)
     return Series(N=N, K=K, S_r=S_r, U=U, J=J, traj=traj_all, y=yv.astype(np.complex64),
                   turn=turns, truth=truth, coils=coils, scale=scale)
 
