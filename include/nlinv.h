@@ -202,6 +202,21 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
                        double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
 
+/* Channel compression (Sec. 3.1, preprocessing): virtual channels
+ * d_y[b][j][s] = sum_p d_cc[j][p] d_yp[b][p][s] of the J_phys receive channels.
+ *   d_cc [J][J_phys] (J of the plan), d_yp [B][J_phys][S], d_y [B][J][S];
+ *   1 <= J_phys <= 128.  FP64 sums. */
+int nlinv_compress(nlinv_plan plan, const nlinv_c64* d_cc, int32_t J_phys,
+                   const nlinv_c64* d_yp, nlinv_c64* d_y);
+
+/* Calibration of the compression (Sec. 3.1): d_cc [J][J_phys] gets, as rows,
+ * the conjugated eigenvectors of the channel covariance y0 y0^H of one frame
+ * d_y0 [J_phys][S] for its J largest eigenvalues (principal components; each
+ * row is defined up to a phase).  The covariance is formed on the GPU in
+ * FP64, the Hermitian eigenproblem (J_phys x J_phys) solved on the host by
+ * Jacobi rotations; blocks the host.  J <= J_phys <= 128. */
+int nlinv_compression_matrix(nlinv_plan plan, const nlinv_c64* d_y0, int32_t J_phys, nlinv_c64* d_cc);
+
 /* Adjoint of the coil synthesis c_j = W^-1 c_hat_j (Sec. 2.2, Sec. 3.2):
  * d_xhat [B][X] gets the image block 0 and the coil blocks
  * W^-H c_j = D_W^-1 crop_{G_c} F_u pad_G c_j of d_coils [B][J][R][R].

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "nlinv_eig.h"
 #include "nlinv_internal.h"
 
 using nlv::Bufs;
@@ -143,7 +144,7 @@ void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, COV, total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -238,6 +239,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->KBN = take(S.kb ? (size_t)S.U * 8 : 0);
   L->KBC = take(S.kb ? R * 4 : 0);
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
+  L->COV = take((size_t)nlv::MAX_JP * nlv::MAX_JP * c16);
   L->total = off;
   return NLINV_OK;
 }
@@ -463,6 +465,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.kbn_host = plan->kbn_host.data();
   w.kbc = reinterpret_cast<float*>(base + L.KBC);
   w.KG = reinterpret_cast<float2*>(base + L.KG);
+  w.cov = reinterpret_cast<double2*>(base + L.COV);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -819,6 +822,47 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
   NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, w.IMG, w.CO, xh, nullptr, nullptr, 0.0));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, xh, nullptr, 0.0, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, dx));
+  return NLINV_OK;
+}
+
+int nlinv_compress(nlinv_plan plan, const nlinv_c64* d_cc, int32_t J_phys, const nlinv_c64* d_yp,
+                   nlinv_c64* d_y) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_cc, "d_cc"));
+  NLV_CHECK(check_ptr(plan, d_yp, "d_yp"));
+  NLV_CHECK(check_ptr(plan, d_y, "d_y"));
+  if (J_phys < 1 || J_phys > nlv::MAX_JP) return fail(plan, NLINV_E_ARG, "J_phys must be in [1, 128]");
+  NLV_HIP(plan, nlv::launch_compress(plan->s, plan->stream, reinterpret_cast<const float2*>(d_cc), J_phys,
+                                     reinterpret_cast<const float2*>(d_yp), reinterpret_cast<float2*>(d_y)));
+  return NLINV_OK;
+}
+
+int nlinv_compression_matrix(nlinv_plan plan, const nlinv_c64* d_y0, int32_t J_phys, nlinv_c64* d_cc) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_y0, "d_y0"));
+  NLV_CHECK(check_ptr(plan, d_cc, "d_cc"));
+  const Shape& s = plan->s;
+  if (J_phys < s.J || J_phys > nlv::MAX_JP) return fail(plan, NLINV_E_ARG, "J_phys must be in [J, 128]");
+  NLV_HIP(plan, nlv::launch_channel_cov(s, plan->stream, reinterpret_cast<const float2*>(d_y0), J_phys, plan->w.cov));
+  std::vector<double2> cov((size_t)J_phys * J_phys);
+  NLV_HIP(plan, hipMemcpyAsync(cov.data(), plan->w.cov, cov.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                               plan->stream));
+  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+  std::vector<std::complex<double>> A(cov.size()), V;
+  for (size_t i = 0; i < cov.size(); ++i) A[i] = std::complex<double>(cov[i].x, cov[i].y);
+  std::vector<double> ev;
+  nlv::hermitian_eig(J_phys, A, ev, V);
+  std::vector<int> order(J_phys);
+  for (int i = 0; i < J_phys; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] > ev[b]; });
+  std::vector<float2> cc((size_t)s.J * J_phys);
+  for (int j = 0; j < s.J; ++j)
+    for (int p = 0; p < J_phys; ++p) {
+      const std::complex<double> v = std::conj(V[(size_t)p * J_phys + order[j]]);
+      cc[(size_t)j * J_phys + p] = make_float2((float)v.real(), (float)v.imag());
+    }
+  NLV_HIP(plan, hipMemcpyAsync(d_cc, cc.data(), cc.size() * sizeof(float2), hipMemcpyHostToDevice, plan->stream));
+  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
   return NLINV_OK;
 }
 

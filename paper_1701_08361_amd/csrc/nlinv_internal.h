@@ -68,6 +68,7 @@ struct Bufs {
   const int2* kbn_host;  // the same counts on the host (launch sizes)
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
+  double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
 };
 
 // Grid-size specific launchers (one table per supported G).
@@ -126,5 +127,9 @@ hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const floa
 hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
                             float2* y);
 hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int turn);
+// channel compression y [B][J][S] = cc [J][Jp] x yp [B][Jp][S]; covariance of one frame [Jp][S]
+constexpr int MAX_JP = 128;
+hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y);
+hipError_t launch_channel_cov(const Shape& s, hipStream_t st, const float2* y0, int Jp, double2* cov);
 
 }  // namespace nlv

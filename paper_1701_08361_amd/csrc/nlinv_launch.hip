@@ -428,6 +428,66 @@ hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int i
   return hipGetLastError();
 }
 
+// Channel compression y[b][j][s] = sum_p cc[j][p] yp[b][p][s]: one thread per
+// sample, the matrix in LDS, FP64 sums over the receive channels.
+constexpr int CJ = 16;   // virtual channels per register pass
+__global__ void __launch_bounds__(VT)
+k_compress(const float2* __restrict__ cc, const float2* __restrict__ yp, float2* __restrict__ y, int J, int Jp,
+           int S) {
+  extern __shared__ float2 scc[];                 // [J][Jp]
+  for (int i = threadIdx.x; i < J * Jp; i += VT) scc[i] = cc[i];
+  __syncthreads();
+  const int s = blockIdx.x * VT + threadIdx.x, b = blockIdx.y;
+  if (s >= S) return;
+  const float2* src = yp + (size_t)b * Jp * S + s;
+  for (int j0 = 0; j0 < J; j0 += CJ) {
+    const int nj = J - j0 < CJ ? J - j0 : CJ;
+    double2 acc[CJ];
+#pragma unroll
+    for (int c = 0; c < CJ; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int p = 0; p < Jp; ++p) {
+      const float2 v = src[(size_t)p * S];
+#pragma unroll
+      for (int c = 0; c < CJ; ++c) {
+        if (c < nj) {
+          const float2 m = scc[(j0 + c) * Jp + p];
+          acc[c].x += (double)m.x * v.x - (double)m.y * v.y;
+          acc[c].y += (double)m.x * v.y + (double)m.y * v.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CJ; ++c)
+      if (c < nj) y[((size_t)b * J + j0 + c) * S + s] = make_float2((float)acc[c].x, (float)acc[c].y);
+  }
+}
+
+// Channel covariance cov[p][q] = sum_s y0[p][s] conj(y0[q][s]) (FP64, fixed order).
+__global__ void __launch_bounds__(VT)
+k_channel_cov(const float2* __restrict__ y0, double2* __restrict__ cov, int Jp, int S) {
+  __shared__ double sh[2 * VT];
+  const int p = blockIdx.x / Jp, q = blockIdx.x % Jp;
+  double sr = 0.0, si = 0.0;
+  for (int s = threadIdx.x; s < S; s += VT) {
+    const float2 a = y0[(size_t)p * S + s], c = y0[(size_t)q * S + s];
+    sr += (double)a.x * c.x + (double)a.y * c.y;
+    si += (double)a.y * c.x - (double)a.x * c.y;
+  }
+  const double2 t = block_sum2_waves<VT>(sr, si, sh);
+  if (threadIdx.x == 0) cov[blockIdx.x] = t;
+}
+
+hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y) {
+  dim3 grid((s.S + VT - 1) / VT, s.B);
+  k_compress<<<grid, VT, (size_t)s.J * Jp * sizeof(float2), st>>>(cc, yp, y, s.J, Jp, s.S);
+  return hipGetLastError();
+}
+
+hipError_t launch_channel_cov(const Shape& s, hipStream_t st, const float2* y0, int Jp, double2* cov) {
+  k_channel_cov<<<Jp * Jp, VT, 0, st>>>(y0, cov, Jp, s.S);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
                            double alpha, float2* out, bool image_block) {
   k_finalize<<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J, s.R * s.R, s.X,

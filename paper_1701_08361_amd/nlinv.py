@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
         "nlinv_apply_DFH": [_P, _P, _P, _P, _P],
         "nlinv_apply_normal": [_P, _P, _P, ctypes.c_double, _P, _P],
         "nlinv_apply_WH": [_P, _P, _P],
+        "nlinv_compress": [_P, _P, _I, _P, _P],
+        "nlinv_compression_matrix": [_P, _P, _I, _P],
         "nlinv_coils": [_P, _P, _P, _P],
         "nlinv_sync": [_P],
         "nlinv_set_graphs": [_P, _I],
@@ -294,6 +296,29 @@ class Plan:
         _check(self.lib.nlinv_apply_DFH(self.handle, self._ptr(traj), self._ptr(xhat), self._ptr(dy),
                                         self._ptr(dx)), self.handle)
         return dx
+
+    def compression_matrix(self, y0, cc=None):
+        """Compression transform [J][J_phys] from one calibration frame y0 [J_phys][S]."""
+        torch = self.torch
+        Jp = int(y0.shape[0])
+        self._t(y0, torch.complex64, (Jp, self.S), "y0")
+        cc = self.empty(self.J, Jp) if cc is None else cc
+        self._t(cc, torch.complex64, (self.J, Jp), "cc")
+        self._stream_sync()
+        _check(self.lib.nlinv_compression_matrix(self.handle, self._ptr(y0), Jp, self._ptr(cc)), self.handle)
+        return cc
+
+    def compress(self, cc, yp, y=None):
+        """Virtual channels y [B][J][S] = cc [J][J_phys] x yp [B][J_phys][S]."""
+        torch = self.torch
+        Jp = int(cc.shape[1])
+        self._t(cc, torch.complex64, (self.J, Jp), "cc")
+        self._t(yp, torch.complex64, (self.B, Jp, self.S), "yp")
+        y = self.empty(self.B, self.J, self.S) if y is None else y
+        self._t(y, torch.complex64, (self.B, self.J, self.S), "y")
+        self._stream_sync()
+        _check(self.lib.nlinv_compress(self.handle, self._ptr(cc), Jp, self._ptr(yp), self._ptr(y)), self.handle)
+        return y
 
     def apply_WH(self, coils, xhat=None):
         """Adjoint of the coil synthesis: image block 0, coil blocks W^-H c_j."""
