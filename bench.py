@@ -70,6 +70,17 @@ def measured_traffic(kind: str):
 
 # Mixed sizes: (N, J, K, series) per shape, 16 series in all
 MIXED = [(128, 8, 11, 5), (160, 10, 15, 6), (192, 16, 21, 5)]
+# Streaming slices: (N, J virtual, J_phys receive channels, K)
+SLICES = [(128, 8, 20, 9), (160, 10, 32, 15), (192, 12, 48, 17), (224, 16, 64, 21)]
+
+
+def _raw_series(args):
+    seed, frames, n, j, jp, k = args
+    from threadpoolctl import threadpool_limits
+    from paper_1701_08361_amd import synth
+    with threadpool_limits(1):
+        s = synth.real_time_series(seed=seed, N=n, J=j, J_phys=jp, K=k, U=U, frames=frames, compress=False)
+    return s.traj, s.y, s.turn
 
 
 def _series(args):
@@ -375,6 +386,54 @@ def run_diff(torch, nl, data, steps, newton, cg):
     return fwd, tot, gy, ga
 
 
+def run_pipeline(torch, raw, periods, period_ms, shared, graphs):
+    """Slices of SLICES streamed through paper_1701_08361_amd.serve.Server at
+    1000 / period_ms frames/s each: receive-channel samples in pinned host
+    memory at arrival, then copy, compression, gridding, reconstruction and
+    image copy-back.  shared: one copy and one solve stream for all slices
+    (frames in arrival order); else per-slice streams.  Returns latencies (ms,
+    image on the host - arrival) and wall ms."""
+    from paper_1701_08361_amd import serve
+    srv = serve.Server(budget_bytes=32 << 30, graphs=graphs, shared_streams=shared)
+    names, host, trajs, turns = [], {}, {}, {}
+    for (n, j, jp, k), (traj, y, turn) in zip(SLICES, raw):
+        name = f"{n}px"
+        tr = torch.from_numpy(traj).cuda()
+        srv.admit(name, n, j, jp, k, U, tr[:U], torch.from_numpy(y[0]).cuda(), newton=M, cg=C)
+        host[name] = torch.from_numpy(y).pin_memory()
+        trajs[name], turns[name] = tr, turn
+        names.append(name)
+    F = min(len(turns[nm]) for nm in names)
+
+    def period(i):
+        evs = []
+        for nm in names:
+            f = i % F
+            evs.append(srv.submit(nm, host[nm][f], trajs[nm][f], int(turns[nm][f]))[0])
+        return evs
+
+    for i in range(2 * U):                   # warm-up: graphs of every (turn, state buffer)
+        period(i)
+    srv.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    done = []
+    for i in range(periods):
+        arrival = i * period_ms
+        now = (time.perf_counter() - t0) * 1e3
+        if now < arrival:
+            time.sleep((arrival - now) / 1e3)
+        for ev in period(2 * U + i):
+            done.append((ev, arrival))
+    srv.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    lat = [start.elapsed_time(ev) - a for ev, a in done]
+    for nm in names:
+        srv.release(nm)
+    return lat, wall
+
+
 def pct(v, q):
     v = sorted(v)
     k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
@@ -431,6 +490,8 @@ def main():
     ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
     ap.add_argument("--diff-steps", type=int, default=2,
                     help="timed forward + backward passes of the unrolled 5 x 20 reconstruction (0 = skip)")
+    ap.add_argument("--pipeline-periods", type=int, default=150,
+                    help="timed periods of the streaming pipeline (4 slices, receive channels; 0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
     args = ap.parse_args()
@@ -466,6 +527,14 @@ def main():
         for (n, j, k, ns) in MIXED:
             mixed_data.append((n, j, k, res[q:q + ns]))
             q += ns
+    raw_data = None
+    if args.pipeline_periods > 0 and args.mode == "both" and not args.fast:
+        jobs = [(200 + q, 2 * U + 10, n, j, jp, k) for q, (n, j, jp, k) in enumerate(SLICES)]
+        if args.workers > 1:
+            with mp.get_context("fork").Pool(min(args.workers, len(jobs))) as pool:
+                raw_data = pool.map(_raw_series, jobs)
+        else:
+            raw_data = [_raw_series(a) for a in jobs]
     t_gen = time.perf_counter() - t_gen
 
     cpu = None if args.no_cpu else cpu_baseline()
@@ -564,6 +633,17 @@ def main():
                     "loss ||image - phantom||^2; gradients w.r.t. the data and alpha_0",
             "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50),
             "grad_norm_data": gy, "grad_alpha0": ga}
+    if raw_data is not None:
+        pipe = {"slices": [{"N": n, "J": j, "J_phys": jp, "K": k} for (n, j, jp, k) in SLICES],
+                "fps_per_slice": args.serve_fps, "periods": args.pipeline_periods,
+                "steps": "pinned host samples -> copy -> channel compression -> gridding -> "
+                         "reconstruction (7 x 20) -> image to host"}
+        for name, shared in (("shared_streams", True), ("per_slice_streams", False)):
+            lat, wall = run_pipeline(torch, raw_data, args.pipeline_periods, 1e3 / args.serve_fps, shared,
+                                     not args.no_graphs)
+            pipe[name] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
+                          "fps": len(lat) / (wall / 1e3)}
+        out["serving_pipeline"] = pipe
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],
