@@ -307,8 +307,7 @@ int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
   const Partials none{};
   NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, plan->w, plan->stream, xh); }));
   NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-            return plan->t->cols_fwd(s, plan->w, plan->stream, 0, co, xh, nullptr, nullptr, nullptr,
-                                        none, nullptr);
+            return plan->t->cols_fwd(s, plan->w, plan->stream, 0, co, xh, nullptr, nullptr);
           }));
   return NLINV_OK;
 }
@@ -575,7 +574,7 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
     // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
     NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, w, st, xh); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-              return plan->t->cols_fwd(s, w, st, 0, w.CO, xh, nullptr, nullptr, nullptr, none, w.U2);
+              return plan->t->cols_fwd(s, w, st, 0, w.CO, xh, nullptr, w.U2);
             }));
     NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
@@ -598,8 +597,7 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
                                              upd ? pc : nullptr, sc);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-                return plan->t->cols_fwd(s, w, st, 1, w.CO, xh, upd ? pp : pc, upd ? w.Rv : nullptr,
-                                         upd ? pc : nullptr, sc, w.U2);
+                return plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pc, w.U2);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
       NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
@@ -781,7 +779,7 @@ int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat,
   const float2* xh = reinterpret_cast<const float2*>(d_xhat);
   const Partials none{};
   NLV_HIP(plan, plan->t->coil_rows(s, w, plan->stream, xh));
-  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 2, w.CO, xh, nullptr, nullptr, nullptr, none, w.IMG));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 2, w.CO, xh, nullptr, w.IMG));
   NLV_HIP(plan, nlv::launch_nudft_fwd(s, plan->stream, d_traj, w.IMG, reinterpret_cast<float2*>(d_y)));
   return NLINV_OK;
 }
@@ -801,7 +799,7 @@ int nlinv_apply_DF(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat
   NLV_CHECK(coils_into(plan, xh, w.CO));
   NLV_HIP(plan, nlv::launch_to_double(s, plan->stream, w.Pv[0], dx));
   NLV_HIP(plan, plan->t->coil_rows_cg(s, w, plan->stream, w.Pv[0], nullptr, nullptr, none));
-  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 3, w.CO, xh, w.Pv[0], nullptr, nullptr, none, w.IMG));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 3, w.CO, xh, w.Pv[0], w.IMG));
   NLV_HIP(plan, nlv::launch_nudft_fwd(s, plan->stream, d_traj, w.IMG, reinterpret_cast<float2*>(d_dy)));
   return NLINV_OK;
 }
@@ -900,7 +898,7 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
   double2* pd = w.Pv[0];
   NLV_HIP(plan, nlv::launch_to_double(s, st, pd, p));
   NLV_HIP(plan, plan->t->coil_rows_cg(s, w, st, pd, nullptr, nullptr, none));
-  NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pd, nullptr, nullptr, none, w.U2));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pd, w.U2));
   NLV_HIP(plan, plan->t->toep_rows(s, w, st, turns));
   NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr, pd, alpha));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, pd, xh, nullptr, alpha, w.Q, nullptr));

@@ -76,14 +76,14 @@ struct GTable {
   // coil spectra of the float32 unknowns -> U1 (W^-1 along x)
   hipError_t (*coil_rows)(const Shape&, const Bufs&, hipStream_t, const float2* src);
   // same on a float64 CG direction; with rsrc != nullptr the update p = r + beta p_old
-  // is fused (src = p_old, result written to pdst)
+  // is fused (src = p_old, the whole new direction, rho block included, written to pdst)
   hipError_t (*coil_rows_cg)(const Shape&, const Bufs&, hipStream_t, const double2* src,
                              const double2* rsrc, double2* pdst, Partials sc);
   // column pass on U1.  mode 0: coils c_j -> co, u = rho c_j -> U2 (out may be null)
   // mode 1: u = c_j d_rho + rho d_c_j -> U2; mode 2: coils -> co, u = rho c_j -> out (image)
-  // mode 3: u = c_j d_rho + rho d_c_j -> out (image).  psrc: float64 direction.
+  // mode 3: u = c_j d_rho + rho d_c_j -> out (image).  pv: float64 direction (modes 1, 3).
   hipError_t (*cols_fwd)(const Shape&, const Bufs&, hipStream_t, int mode, float2* co, const float2* xh,
-                         const double2* psrc, const double2* rsrc, double2* pdst, Partials sc, void* out);
+                         const double2* pv, void* out);
   // row pass: FFT, multiply by the PSF kernel of each item's turn, inverse FFT (in place on U2)
   hipError_t (*toep_rows)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns);
   // column pass back: mode 0 normal (dot partials to pq), 1 residual (z - T u), 2 adjoint of an

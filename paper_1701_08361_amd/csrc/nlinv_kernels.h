@@ -138,19 +138,49 @@ __device__ __forceinline__ double beta_of(const Partials& sc, int b, double* sh)
 
 // ---------------------------------------------------------------------------
 // coil_rows: W^-1 along x.  Line (b, j, i): G_c weighted coil coefficients of
-// spectrum row i -> R image columns.  Optional fused p = r + beta p_old.
+// spectrum row i -> R image columns.  Optional fused p = r + beta p_old; the
+// rho block of the direction is updated by nr further blocks per item, so the
+// whole new direction is in pdst before the column pass reads it.
 // ---------------------------------------------------------------------------
+constexpr int RHO_PER_THREAD = 8;   // rho-block elements per thread of the update blocks
+
 template <int G, class V>
 __global__ void __launch_bounds__(row_threads<G>())
 k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
             Partials sc, const float* __restrict__ dinv, const double2* __restrict__ tw,
-            double2* __restrict__ U1, int J, long long X, int nb) {
+            double2* __restrict__ U1, int J, long long X, int nb, int nr) {
   using T = Team<G>;
   constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
   __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[NTH];
-  // nb blocks per item, each RT of the item's J * GC lines
-  const int b = blockIdx.x / nb, chunk = blockIdx.x - b * nb;
+  // nb line blocks then nr rho-update blocks per item, each line block RT of
+  // the item's J * GC lines
+  const int b = blockIdx.x / (nb + nr), chunk = blockIdx.x - b * (nb + nr);
+  if constexpr (std::is_same<V, double2>::value) {
+    if (chunk >= nb) {   // block-uniform
+      constexpr int E = RHO_PER_THREAD;
+      const double2* ps = src + (size_t)b * X;
+      const double2* rs = rsrc + (size_t)b * X;
+      double2* pd = pdst + (size_t)b * X;
+      const int e0 = (chunk - nb) * NTH * E + (int)threadIdx.x;
+      double2 po[E], ro[E];
+      sfor<0, E>([&](auto c) {
+        constexpr int k = decltype(c)::value;
+        const int e = e0 + k * NTH;
+        if (e < R * R) {
+          po[k] = ps[e];
+          ro[k] = rs[e];
+        }
+      });
+      const double beta = beta_of<NTH>(sc, b, sh);
+      sfor<0, E>([&](auto c) {
+        constexpr int k = decltype(c)::value;
+        const int e = e0 + k * NTH;
+        if (e < R * R) pd[e] = make_double2(ro[k].x + beta * po[k].x, ro[k].y + beta * po[k].y);
+      });
+      return;
+    }
+  }
   const int rl0 = (int)threadIdx.x / T::SIZE, l0 = chunk * RT + rl0;
   const bool act = rl0 < RT && l0 < J * GC;
   const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
@@ -210,27 +240,28 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
 // cols_fwd: W^-1 along y, coil product, forward FFT along y.
 // MODE 0: coils -> co, u = rho c_j -> out (U2, may be null)
 // MODE 1: u = c_j d_rho + rho d_c_j -> out (U2);  MODE 2 / 3: as 0 / 1 but u -> out (image, float32)
+// pv: the direction (MODE 1 / 3), its rho block already updated by coil_rows.
 // ---------------------------------------------------------------------------
 template <int G, int MODE, class S2>
 __global__ void __launch_bounds__(cols_threads<G>())
 k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2* __restrict__ xh,
-           const double2* __restrict__ psrc, const double2* __restrict__ rsrc, double2* __restrict__ pdst,
-           Partials sc, const double2* __restrict__ tw, void* __restrict__ outp, int J, long long X) {
+           const double2* __restrict__ pv, const double2* __restrict__ tw, void* __restrict__ outp, int J,
+           long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW;
   constexpr bool NORMAL = (MODE == 1 || MODE == 3);
   constexpr bool TO_IMG = (MODE == 2 || MODE == 3);
   __shared__ C lds[TW * T::LDSC];
-  __shared__ double sh[NTH];
   const bool act = (int)threadIdx.x < TW * T::SIZE;
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
-  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
   const int x = tile * TW + col;
   C* L = lds + col * T::LDSC;
-  const bool upd = NORMAL && rsrc != nullptr;
 
-  // every load of the pass is issued before the first reduction or exchange,
-  // so that their latencies overlap (one memory round trip per pass)
+  // the coil-row, rho and coil-image loads are issued before the first exchange,
+  // so that their latencies overlap; the float64 direction is loaded after the
+  // first transform, which keeps the kernel at 160 VGPRs (3 waves per SIMD
+  // instead of 2; measured 18 % faster at batch 16)
   const double2* u1 = U1 + (size_t)bj * GC * R + x;
   C a[T::G2];
   fsA_load<G, SET_COIL>(tl, a, [&](int n) -> C {
@@ -240,7 +271,7 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
   const float2* rho = xh + (size_t)b * X;
   float2* cj = co + (size_t)bj * R * R;
   float2 rv[T::G1], cv[T::G1];
-  double2 dv[T::G1], qv[T::G1];
+  double2 dv[T::G1];
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
@@ -249,19 +280,24 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
         if (iy >= 0) {
           const size_t e = (size_t)iy * R + x;
           rv[k1] = rho[e];
-          if constexpr (NORMAL) {
-            const size_t pe = (size_t)b * X + e;
-            cv[k1] = cj[e];
-            dv[k1] = psrc[pe];
-            if (upd) qv[k1] = rsrc[pe];
-          }
+          if constexpr (NORMAL) cv[k1] = cj[e];
         }
       }
     });
   }
-  const double beta = upd ? beta_of<NTH>(sc, b, sh) : 0.0;
   C v[T::G1];
   fsA_regs<G, +1, SET_IMG>(tl, L, tw, a, v);
+  if constexpr (NORMAL) {
+    if (tl < T::G2) {
+      sfor<0, T::G1>([&](auto c) {
+        constexpr int k1 = decltype(c)::value;
+        if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+          const int iy = img_idx<G>(T::G2 * k1 + tl);
+          if (iy >= 0) dv[k1] = pv[(size_t)b * X + (size_t)iy * R + x];
+        }
+      });
+    }
+  }
 
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
@@ -276,14 +312,7 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
           cj[e] = cf;
           u = cmul(r, to_d(cf));   // the stored (float32) coil image, as later passes read it
         } else {
-          const size_t pe = (size_t)b * X + e;
-          double2 dr = dv[k1];
-          if (upd) {
-            const double2 rr = qv[k1];
-            dr = make_double2(rr.x + beta * dr.x, rr.y + beta * dr.y);
-            if (j == 0) pdst[pe] = dr;
-          }
-          u = cadd(cmul(to_d(cv[k1]), dr), cmul(r, v[k1]));
+          u = cadd(cmul(to_d(cv[k1]), dv[k1]), cmul(r, v[k1]));
         }
         if constexpr (TO_IMG) static_cast<float2*>(outp)[(size_t)bj * R * R + e] = to_f(u);
       }
@@ -710,34 +739,34 @@ struct GLaunch {
 
   static hipError_t coil_rows(const Shape& s, const Bufs& w, hipStream_t st, const float2* src) {
     k_coil_rows<G, float2><<<s.B * s.NX3, TH_ROW1, 0, st>>>(src, nullptr, nullptr, Partials{},
-                                                                          w.dinv, w.tw, w.U1, s.J, s.X, s.NX3);
+                                                                          w.dinv, w.tw, w.U1, s.J, s.X, s.NX3, 0);
     return hipGetLastError();
   }
   static hipError_t coil_rows_cg(const Shape& s, const Bufs& w, hipStream_t st, const double2* src,
                                  const double2* rsrc, double2* pdst, Partials sc) {
-    k_coil_rows<G, double2><<<s.B * s.NX3, TH_ROW1, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
-                                                                           w.tw, w.U1, s.J, s.X, s.NX3);
+    constexpr int PER_BLOCK = TH_ROW1 * RHO_PER_THREAD;
+    const int nr = rsrc ? (s.R * s.R + PER_BLOCK - 1) / PER_BLOCK : 0;
+    k_coil_rows<G, double2><<<s.B * (s.NX3 + nr), TH_ROW1, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
+                                                                                  w.tw, w.U1, s.J, s.X, s.NX3, nr);
     return hipGetLastError();
   }
   template <class S2>
   static hipError_t cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
-                               const float2* xh, const double2* psrc, const double2* rsrc, double2* pdst,
-                               Partials sc, void* out) {
+                               const float2* xh, const double2* pv, void* out) {
     const int blocks = s.B * s.J * s.NT;
     switch (mode) {
-      case 0: k_cols_fwd<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
-      case 1: k_cols_fwd<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
-      case 2: k_cols_fwd<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
-      case 3: k_cols_fwd<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, psrc, rsrc, pdst, sc, w.tw, out, s.J, s.X); break;
+      case 0: k_cols_fwd<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
+      case 1: k_cols_fwd<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
+      case 2: k_cols_fwd<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
+      case 3: k_cols_fwd<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   static hipError_t cols_fwd(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
-                             const float2* xh, const double2* psrc, const double2* rsrc, double2* pdst,
-                             Partials sc, void* out) {
-    return s.fast ? cols_fwd_t<float2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out)
-                  : cols_fwd_t<double2>(s, w, st, mode, co, xh, psrc, rsrc, pdst, sc, out);
+                             const float2* xh, const double2* pv, void* out) {
+    return s.fast ? cols_fwd_t<float2>(s, w, st, mode, co, xh, pv, out)
+                  : cols_fwd_t<double2>(s, w, st, mode, co, xh, pv, out);
   }
   template <class S2>
   static hipError_t toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
