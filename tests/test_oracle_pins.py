@@ -5,6 +5,8 @@ identities of the method and numbers printed in the paper.
 Each test names the passage it follows.  Sizes are tiny so the whole file
 runs in seconds on the CPU.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -165,12 +167,28 @@ def test_sobolev_weight_printed_values():
     assert 1.0 / w[0, 0] == pytest.approx(5.3e-24, rel=2e-2)
 
 
-@pytest.mark.parametrize("N,gamma,G,Gc", [(128, 1.5, 384, 96), (144, 1.5, 432, 108),
-                                          (160, 1.51875, 486, 121), (170, 1.50588, 512, 128),
-                                          (256, 1.53125, 784, 196)])
-def test_grid_sizes_from_tables(N, gamma, G, Gc):
-    """Tables oversampling_ratio and tiny: G = 2 gamma N (rounded), G_c = floor(G/4)."""
+def _printed_grid_sizes():
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid_sizes.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            n, gf, gam, g, gcf, gc = line.split()
+            rows.append((int(n), int(gf), float(gam), int(g), int(gcf), int(gc)))
+    return rows
+
+
+def test_printed_grid_sizes_fixture_is_complete():
+    assert [r[0] for r in _printed_grid_sizes()] == [128, 144, 160, 170, 256]
+
+
+@pytest.mark.parametrize("N,G_fixed,gamma,G,Gc_full,Gc", _printed_grid_sizes())
+def test_grid_sizes_from_tables(N, G_fixed, gamma, G, Gc_full, Gc):
+    """Tables oversampling_ratio and tiny: G = 2 gamma N (rounded; gamma = 1.5
+    for the fixed column), the uncropped coil grid is G, and the oracle's
+    cropped coil grid is G_c = floor(G / 4)."""
+    assert round(2 * 1.5 * N) == G_fixed
     assert round(2 * gamma * N) == G
+    assert Gc_full == G
     R, G2, Gc2 = O.sizes(N, G)
     assert (G2, Gc2) == (G, Gc) and R == G // 2 and R >= N
 
