@@ -357,22 +357,27 @@ def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
 
 def run_diff(torch, nl, data, steps, newton, cg):
     """Unrolled, checkpointed IRGNM of frame 0 (batch 1) with the loss
-    ||image - phantom||^2 and its gradient with respect to the data and alpha_0.
-    Returns (forward ms, forward + backward ms) per step and the gradient norms."""
+    ||image - phantom||^2 and its gradient with respect to the data, alpha_0
+    and the Sobolev weight's a and l (at the plan's weight, a = 880, l = 16).
+    Returns (forward ms, forward + backward ms) per step and the gradients."""
+    from paper_1701_08361_amd import autograd as AG
     from paper_1701_08361_amd import unrolled as UR
     plan = nl.Plan(N, J, K, U=U)
     traj = torch.from_numpy(data[0][0][0:1]).cuda()
     y0 = torch.from_numpy(data[0][1][0:1]).cuda()
     target = torch.from_numpy(data[0][3]).cuda().float()
     fwd, tot = [], []
-    gy = ga = None
+    grads = {}
     for i in range(steps + 1):
         y = y0.clone().requires_grad_(True)
         a0 = torch.tensor(1.0, device="cuda", requires_grad=True)
+        sa = torch.tensor(880.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        sl = torch.tensor(16.0, dtype=torch.float64, device="cuda", requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x = UR.reconstruct(plan, traj, y, N, newton=newton, cg_iters=cg, alpha0=a0)
-        loss = ((UR.image(plan, x, N)[0] - target) ** 2).sum()
+        m = AG.Reweighted(plan, plan.G, plan.Gc, plan.R, J, sa, sl)
+        x = UR.reconstruct(m, traj, y, N, newton=newton, cg_iters=cg, alpha0=a0)
+        loss = ((UR.image(m, x, N)[0] - target) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss.backward()
@@ -381,9 +386,10 @@ def run_diff(torch, nl, data, steps, newton, cg):
         if i > 0:                       # the first pass is a warm-up
             fwd.append((t1 - t0) * 1e3)
             tot.append((t2 - t0) * 1e3)
-        gy, ga = float(y.grad.abs().pow(2).sum().sqrt()), float(a0.grad)
+        grads = {"grad_norm_data": float(y.grad.abs().pow(2).sum().sqrt()), "grad_alpha0": float(a0.grad),
+                 "grad_sobolev_a": float(sa.grad), "grad_sobolev_l": float(sl.grad)}
     plan.close()
-    return fwd, tot, gy, ga
+    return fwd, tot, grads
 
 
 def run_pipeline(torch, raw, periods, period_ms, shared, graphs):
@@ -627,12 +633,12 @@ def main():
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
     if plain_data is not None and args.diff_steps > 0 and not args.fast:
-        fwd, tot, gy, ga = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
+        fwd, tot, grads = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
         out["differentiation"] = {
             "form": "unrolled IRGNM, 5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
-                    "loss ||image - phantom||^2; gradients w.r.t. the data and alpha_0",
-            "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50),
-            "grad_norm_data": gy, "grad_alpha0": ga}
+                    "loss ||image - phantom||^2; gradients w.r.t. the data, alpha_0 and the Sobolev weight's "
+                    "a and l (w = (1 + a|k|^2)^l at 880, 16)",
+            "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50), **grads}
     if raw_data is not None:
         pipe = {"slices": [{"N": n, "J": j, "J_phys": jp, "K": k} for (n, j, jp, k) in SLICES],
                 "fps_per_slice": args.serve_fps, "periods": args.pipeline_periods,

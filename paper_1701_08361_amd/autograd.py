@@ -17,7 +17,8 @@ dL = Re<grad, dx>.
 `ops` is any object with apply_F / apply_DF / apply_DFH(traj, xhat, ...),
 coils(xhat, want_img=False) and apply_WH(coils) in the shapes of
 paper_1701_08361_amd.nlinv.Plan (xhat [B][X], data [B][J][S], coil images
-[B][J][R][R]).
+[B][J][R][R]).  Reweighted gives the same operators under another Sobolev
+weight, differentiable in its parameters.
 """
 from __future__ import annotations
 
@@ -85,6 +86,73 @@ class _Coils(torch.autograd.Function):
 def coils(ops, xhat):
     """Coil images c_j = W^-1 c_hat_j [B][J][R][R] (linear in the coil block)."""
     return _Coils.apply(xhat, ops)
+
+
+class Reweighted:
+    """The operators of the model under another Sobolev weight
+    w'(k) = (1 + a |k|^2)^l (Sec. 3.2, Fig. weight_func), differentiable in a
+    and l, built from operators `ops` of the reference weight
+    w(k) = (1 + a_ref |k|^2)^l_ref.
+
+    The coil synthesis divides the coil spectrum by the weight before the
+    inverse transform, so W'^-1 c_hat = W^-1 (c_hat . w / w'): with the real
+    diagonal D = diag(1 on rho, w / w' on every coil block),
+        F'(x) = F(D x),  DF'_x(dx) = DF_{D x}(D dx),  DF'^H_x(dy) = D DF^H_{D x}(dy),
+        coils'(x) = coils(D x).
+    D is formed here from a and l (tensors that may require grad) on the
+    centred G_c x G_c spectrum, k = kappa / G, in the layout of x_hat; the
+    operator calls themselves go through the autograd functions above.
+    """
+
+    def __init__(self, ops, G, Gc, R, J, a, l, a_ref=880.0, l_ref=16.0):
+        self.ops, self.X, self.R = ops, ops.X, R
+        dev = a.device if torch.is_tensor(a) else None
+        kap = (torch.arange(Gc, dtype=torch.float64, device=dev) - Gc // 2) / G
+        k2 = kap[:, None] ** 2 + kap[None, :] ** 2
+        a = torch.as_tensor(a, dtype=torch.float64, device=dev)
+        l = torch.as_tensor(l, dtype=torch.float64, device=dev)
+        # w / w' in logarithms: the weights themselves reach 1e23 at the spectrum's corners
+        ratio = torch.exp(l_ref * torch.log1p(a_ref * k2) - l * torch.log1p(a * k2))
+        self.d = torch.cat([torch.ones(R * R, dtype=torch.float64, device=dev), ratio.reshape(-1).repeat(J)])
+
+    def _scale(self, x):
+        return x * self.d.to(device=x.device, dtype=x.real.dtype)
+
+    def F(self, traj, xhat):
+        return F(self.ops, traj, self._scale(xhat))
+
+    def DF(self, traj, xhat, dx):
+        return DF(self.ops, traj, self._scale(xhat), self._scale(dx))
+
+    def DFH(self, traj, xhat, dy):
+        return self._scale(DFH(self.ops, traj, self._scale(xhat), dy))
+
+    def coils(self, xhat):
+        return coils(self.ops, self._scale(xhat))
+
+
+class Plain:
+    """The operators of `ops` in the interface of Reweighted."""
+
+    def __init__(self, ops):
+        self.ops, self.X = ops, ops.X
+
+    def F(self, traj, xhat):
+        return F(self.ops, traj, xhat)
+
+    def DF(self, traj, xhat, dx):
+        return DF(self.ops, traj, xhat, dx)
+
+    def DFH(self, traj, xhat, dy):
+        return DFH(self.ops, traj, xhat, dy)
+
+    def coils(self, xhat):
+        return coils(self.ops, xhat)
+
+
+def model(ops):
+    """Reweighted / Plain models pass through; raw operators are wrapped."""
+    return ops if isinstance(ops, (Reweighted, Plain)) else Plain(ops)
 
 
 def F(ops, traj, xhat):

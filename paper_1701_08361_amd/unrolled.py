@@ -9,7 +9,9 @@ alpha_0.  The operators run through the C-ABI (exact non-uniform DFT, no PSF
 convolution: F and F^H separately, which the adjoint rules need); the CG
 vector algebra of this form runs as torch operations on the device.  Each
 Newton step is checkpointed: only the iterates x_n are kept between the
-forward and the backward pass, the CG iterations are recomputed.
+forward and the backward pass, the CG iterations are recomputed.  `ops` may
+be an autograd.Reweighted model, which adds gradients with respect to the
+Sobolev weight's parameters.
 
 Newton steps and CG iterations follow the reading of the plain solver:
 Re<., .> inner products, a = 0 when Re<p, q> = 0, beta = 0 when the previous
@@ -42,12 +44,13 @@ def unit_start(B, R, X, device, dtype=torch.complex64):
 
 def newton_step(ops, traj, x, xprev, y, alpha, cg_iters):
     """x + h with h from C CG iterations on the Newton system at x."""
-    b = AG.DFH(ops, traj, x, y - AG.F(ops, traj, x)) - alpha * (x - xprev)
+    m = AG.model(ops)
+    b = m.DFH(traj, x, y - m.F(traj, x)) - alpha * (x - xprev)
     h = torch.zeros_like(b)
     r, p = b, b
     rr = _rdot(r, r)
     for _ in range(cg_iters):
-        q = AG.DFH(ops, traj, x, AG.DF(ops, traj, x, p)) + alpha * p
+        q = m.DFH(traj, x, m.DF(traj, x, p)) + alpha * p
         a = _safe_div(rr, _rdot(p, q))
         h = h + a[:, None] * p
         r = r - a[:, None] * q
@@ -80,5 +83,5 @@ def image(ops, x, R, eps=1e-12):
     """|rho| sqrt(sum_j |c_j|^2) [B][R][R], differentiable (eps keeps the square
     root's derivative finite where every coil vanishes)."""
     rho = x[:, :R * R].reshape(-1, R, R)
-    c = AG.coils(ops, x)
+    c = AG.model(ops).coils(x)
     return rho.abs() * torch.sqrt((c.abs() ** 2).sum(dim=1) + eps)

@@ -122,3 +122,82 @@ def test_unrolled_gradcheck_data_and_alpha():
         return UR.image(ops, x, g.R)
 
     assert torch.autograd.gradcheck(fn, (y, a0), eps=1e-6, atol=1e-5, rtol=1e-4)
+
+
+# --------------------------------------------------------------------------
+# another Sobolev weight (Sec. 3.2, Fig. weight_func), differentiable in a, l
+# --------------------------------------------------------------------------
+
+A_W, L_W = 20.0, 2.0       # a soft weight under test; the operators are built for (880, 16)
+
+
+def _reweighted(ops, g, a=A_W, l=L_W):
+    a = torch.as_tensor(a, dtype=torch.float64)
+    l = torch.as_tensor(l, dtype=torch.float64)
+    return AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
+
+
+def test_reweighted_operators_equal_the_oracle_at_that_weight():
+    """F, DF, DF^H and the coil synthesis rebuilt from the (880, 16) operators
+    equal the oracle's operators defined with w = (1 + 20|k|^2)^2."""
+    ops, traj, g, cx = _setup(B=2, N=8, J=2, K=3, seed=11)
+    g2 = O.Geometry.make(8, 2, a=A_W, l=L_W)
+    ops2 = OracleOps(g2)
+    m = _reweighted(ops, g)
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(np.stack([g2.pack(rng.standard_normal((g2.R, g2.R)) + 0j,
+                                           (rng.standard_normal((g2.J, g2.Gc, g2.Gc)) + 1j) * g2.w[None])
+                                   for _ in range(2)]))
+    dx = torch.from_numpy(np.stack([g2.pack(rng.standard_normal((g2.R, g2.R)) + 1j,
+                                            rng.standard_normal((g2.J, g2.Gc, g2.Gc)) * g2.w[None] + 0j)
+                                    for _ in range(2)]))
+    S = traj.shape[1] * traj.shape[2]
+    dy = cx(2, g.J, S)
+    rel = lambda u, v: float(torch.linalg.norm(u - v) / torch.linalg.norm(v))
+    assert rel(m.F(traj, x), ops2.apply_F(traj, x)) < 1e-12
+    assert rel(m.DF(traj, x, dx), ops2.apply_DF(traj, x, dx)) < 1e-12
+    assert rel(m.DFH(traj, x, dy), ops2.apply_DFH(traj, x, dy)) < 1e-12
+    assert rel(m.coils(x), ops2.coils(x)[0]) < 1e-12
+    # at the reference weight the rescaling is the identity
+    m0 = _reweighted(ops, g, 880.0, 16.0)
+    assert torch.equal(m0.d, torch.ones_like(m0.d))
+
+
+def test_unrolled_reweighted_equals_oracle_reconstruction():
+    """The unrolled IRGNM under (20, 2), from the (880, 16) operators,
+    reproduces the oracle's IRGNM with that weight."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _setup(B=1, N=8, J=2, K=5, seed=5)
+    g2 = O.Geometry.make(8, 2, a=A_W, l=L_W)
+    s = synth.single_frame(seed=5, N=8, J=2, K=5)
+    t = s.traj.astype(np.float64)
+    y = torch.from_numpy(s.y.astype(np.complex128))
+    x = UR.reconstruct(_reweighted(ops, g), torch.from_numpy(t), y, g.R, newton=3, cg_iters=4)
+    P = O.psf_kernel(t[0], g2.R, g2.G)
+    ref = O.reconstruct(g2, O.grid(s.y[0].astype(np.complex128), t[0], g2.R), P, newton=3, cg_iters=4)
+    err = np.linalg.norm(x.detach().numpy()[0] - ref) / np.linalg.norm(ref)
+    assert err < 1e-9, err
+    # and the weight matters: the (880, 16) reconstruction differs
+    ref0 = O.reconstruct(g, O.grid(s.y[0].astype(np.complex128), t[0], g.R), P, newton=3, cg_iters=4)
+    assert np.linalg.norm(ref0 - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_unrolled_gradcheck_sobolev_weight():
+    """Finite-difference check of d image / d (a, l) of the Sobolev weight
+    through 2 Newton steps of 2 CG iterations, each step checkpointed."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _setup(B=1, N=8, J=2, K=3, seed=7)
+    y = 0.3 * cx(1, g.J, traj.shape[1] * traj.shape[2])
+    a = torch.tensor(A_W, dtype=torch.float64, requires_grad=True)
+    l = torch.tensor(L_W, dtype=torch.float64, requires_grad=True)
+
+    def fn(a, l):
+        m = AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
+        x = UR.reconstruct(m, traj[:1], y, g.R, newton=2, cg_iters=2)
+        return UR.image(m, x, g.R)
+
+    # the weight reaches the image: a gradient far from zero is checked
+    ga, gl = torch.autograd.grad(fn(a, l).sum(), (a, l))
+    print(f"d sum(image) / d(a, l) = {float(ga):.3e}, {float(gl):.3e}")
+    assert abs(float(ga)) > 1e-4 and abs(float(gl)) > 1e-3
+    assert torch.autograd.gradcheck(fn, (a, l), eps=1e-5, atol=1e-6, rtol=1e-4)

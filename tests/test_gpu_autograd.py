@@ -188,3 +188,44 @@ def test_unrolled_gradients_match_fp64(torch):
     ey, ea = rel(gy, ry), abs(ga - ra) / abs(ra)
     print(f"loss {L:.6e} vs {Lr:.6e}; grad y rel {ey:.2e}; grad alpha0 {ga:.6e} vs {ra:.6e} (rel {ea:.2e})")
     assert ey < 1e-2 and ea < 1e-2
+
+
+def test_unrolled_sobolev_weight_gradients_match_fp64(torch):
+    """Another Sobolev weight w = (1 + a|k|^2)^l (a = 20, l = 2) built from the
+    plan's (880, 16) operators: the forward image against the oracle's IRGNM
+    defined with that weight, and the gradients of ||image - phantom||^2 with
+    respect to a and l through 3 checkpointed Newton steps of 4 CG iterations,
+    GPU (float32 operators) against the same procedure in float64 on the
+    oracle."""
+    from paper_1701_08361_amd import autograd as AG
+    from paper_1701_08361_amd import unrolled as UR
+    from test_autograd_cpu import OracleOps
+    N, J, K, M, C = 32, 4, 7, 3, 4
+    A, L = 20.0, 2.0
+    print(f"[case] unrolled Sobolev-weight gradients N={N} J={J} K={K} M={M} C={C} a={A} l={L}", flush=True)
+    plan, g, s = _unrolled_case(torch, N, J, K, M, C)
+    truth = s.truth[0] * np.linalg.norm(s.coils.reshape(J, -1), axis=0).reshape(N, N)
+
+    def run(ops, traj, y0, dev, cdt, rdt):
+        a = torch.tensor(A, dtype=torch.float64, device=dev, requires_grad=True)
+        l = torch.tensor(L, dtype=torch.float64, device=dev, requires_grad=True)
+        m = AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
+        y = torch.from_numpy(y0).to(dev, cdt)
+        x = UR.reconstruct(m, traj, y, g.R, newton=M, cg_iters=C)
+        img = UR.image(m, x, g.R)
+        t = torch.from_numpy(truth).to(dev, rdt)
+        loss = ((img[0] - t / t.norm() * img[0].detach().norm()) ** 2).sum()
+        loss.backward()
+        return float(a.grad), float(l.grad), img.detach().cpu().numpy()[0]
+
+    ga, gl, img = run(plan, torch.from_numpy(s.traj).cuda(), s.y, "cuda", torch.complex64, torch.float32)
+    ra, rl, _ = run(OracleOps(g), torch.from_numpy(s.traj.astype(np.float64)), s.y.astype(np.complex128),
+                    "cpu", torch.complex128, torch.float64)
+    g2 = O.Geometry.make(N, J, a=A, l=L)
+    P = O.psf_kernel(s.traj[0], g2.R, g2.G)
+    xr = O.reconstruct(g2, O.grid(s.y[0], s.traj[0], g2.R), P, newton=M, cg_iters=C)
+    e_img = rel(img, O.image(g2, xr))
+    ea, el = abs(ga - ra) / abs(ra), abs(gl - rl) / abs(rl)
+    print(f"image rel {e_img:.2e}; d/da {ga:.6e} vs {ra:.6e} (rel {ea:.2e}); d/dl {gl:.6e} vs {rl:.6e} (rel {el:.2e})")
+    assert e_img < 1e-3
+    assert ea < 1e-2 and el < 1e-2
