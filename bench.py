@@ -392,6 +392,38 @@ def run_diff(torch, nl, data, steps, newton, cg):
     return fwd, tot, grads
 
 
+def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
+    """The autotuner's learning mode on the 160 px series for several series
+    lengths: every setting (T frames per relaxed group = 1..8, A = 1, HIP
+    graphs off / on) reconstructs the first `frames` frames, the database
+    records each rate, and the worst and best settings are reported per
+    length.  Rates include gridding and graph captures; plans and PSF kernels
+    are built before the clock starts."""
+    from paper_1701_08361_amd import autotune as AT
+    traj_all = torch.from_numpy(data[0][0]).cuda()
+    y_all = torch.from_numpy(data[0][1]).cuda()
+    turns_all = [int(t) for t in data[0][2]]
+    db = AT.TuningDB()
+    rows = []
+    for frames in frame_counts:
+        frames = min(frames, traj_all.shape[0])
+        p = dict(mode="single-slice", N=N, J=J, K=K, U=U, frames=frames, newton=M, cg=C)
+        tuner = AT.Autotuner(db, learning=True)
+        if not graphs_allowed:
+            tuner.space = [c for c in tuner.space if not c["graphs"]]
+        tuner.learn(p, lambda c: AT.run_series(nl, torch, traj_all[:frames], y_all[:frames],
+                                               turns_all[:frames], c, M, C, U)[0])
+        hits = db.lookup(p)
+        (bc, bf), (wc, wf) = hits[0], hits[-1]
+        rows.append({"frames": frames, "settings": len(hits),
+                     "worst": {"T": wc["T"], "A": wc["A"], "graphs": wc["graphs"], "fps": wf},
+                     "best": {"T": bc["T"], "A": bc["A"], "graphs": bc["graphs"], "fps": bf},
+                     "all": [[c["T"], c["graphs"], round(f, 1)] for c, f in hits]})
+    return {"form": "learning mode over T = 1..8 frames per relaxed group (l = 5 strict frames first), A = 1, "
+                    "HIP graphs off/on; rate = frames / wall time of the whole series (gridding + reconstruction)",
+            "by_frames": rows}
+
+
 def run_pipeline(torch, raw, periods, period_ms, shared, graphs):
     """Slices of SLICES streamed through paper_1701_08361_amd.serve.Server at
     1000 / period_ms frames/s each: receive-channel samples in pinned host
@@ -500,6 +532,8 @@ def main():
                     help="timed periods of the streaming pipeline (4 slices, receive channels; 0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
+    ap.add_argument("--autotune-frames", default="5,10,25,50",
+                    help="series lengths of the autotuning run (learning mode over all settings; '' = skip)")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -650,6 +684,9 @@ def main():
             pipe[name] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                           "fps": len(lat) / (wall / 1e3)}
         out["serving_pipeline"] = pipe
+    if plain_data is not None and args.autotune_frames and not args.fast:
+        out["autotune"] = run_autotune(torch, nl, plain_data, [int(f) for f in args.autotune_frames.split(",")],
+                                       not args.no_graphs)
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],
