@@ -39,7 +39,8 @@ def test_compress_matches_oracle(torch, N, J, Jp, K, B):
     assert e < 1e-6
 
 
-@pytest.mark.parametrize("N,J,Jp,K", [(32, 4, 9, 5), (160, 10, 30, 15), (64, 16, 64, 13)])
+@pytest.mark.parametrize("N,J,Jp,K", [(32, 4, 9, 5), (160, 10, 30, 15), (64, 16, 64, 13),
+                                      (32, 8, 128, 5)])     # the most receive channels
 def test_compression_matrix_matches_oracle(torch, N, J, Jp, K):
     """Calibration on one receive-channel frame: orthonormal rows spanning the
     oracle's principal subspace (compared as projectors, rows being defined up

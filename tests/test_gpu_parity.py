@@ -59,6 +59,21 @@ def print_case(name, **kw):
 # gridding, coils, PSF convolution
 # ---------------------------------------------------------------------------
 
+def test_grid_ragged_readout(torch):
+    """A readout length that is not 2N (odd, 77 samples per spoke): the
+    Kaiser-Bessel tables and the exact sum against the oracle's sum."""
+    N, J, K, S_r = 32, 3, 7, 77
+    print_case("grid ragged", N=N, J=J, K=K, S_r=S_r)
+    s = synth.single_frame(seed=13, N=N, J=J, K=K, S_r=S_r)
+    assert s.traj.shape[2] == S_r
+    ref = O.grid(s.y[0], s.traj[0], N)
+    for flags in (0, 2):
+        plan = nl().Plan(N, J, K, S_r=S_r, flags=flags)
+        z = host(plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0]))
+        print(f"grid ragged flags={flags}: rel {rel(z[0], ref):.2e}")
+        assert rel(z[0], ref) < 1e-6
+
+
 @pytest.mark.parametrize("N,J,K,seed", [(32, 3, 5, 11), (64, 8, 13, 1), (160, 10, 15, 2)])
 def test_grid_matches_exact_adjoint_nudft(torch, N, J, K, seed):
     """Kaiser-Bessel gridding (turns given, the default) and the exact sum
@@ -115,7 +130,9 @@ def _normal_case(torch, N, J, K, U, B, alpha, seed):
 @pytest.mark.parametrize("N,J,K,U,B,alpha", [
     (32, 2, 5, 1, 1, 0.0), (64, 8, 13, 2, 3, 0.37), (64, 8, 13, 1, 1, 0.0),
     (128, 4, 11, 3, 2, 0.0), (160, 10, 15, 5, 2, 0.125), (192, 3, 9, 1, 1, 0.0),
-    (224, 5, 21, 2, 2, 0.5)])
+    (224, 5, 21, 2, 2, 0.5),
+    (32, 64, 5, 2, 2, 0.1),     # the most channels a plan takes
+    (32, 2, 3, 4, 64, 0.0)])    # the largest batch
 def test_normal_operator(torch, N, J, K, U, B, alpha):
     print_case("normal", N=N, J=J, K=K, U=U, B=B, alpha=alpha)
     _normal_case(torch, N, J, K, U, B, alpha, seed=7 * N + J)
@@ -191,6 +208,7 @@ def test_reconstruct_single_frame_c1(torch):
     (192, 16, 21, 3, 6),    # largest mixed-size configuration (384 grid, 16 coils, 21 spokes)
     (224, 16, 21, 2, 4),    # largest supported grid (448), 16 coils
     (32, 1, 1, 3, 4),       # degenerate: one coil, one spoke
+    (32, 64, 5, 2, 3),      # the most channels a plan takes
 ])
 def test_reconstruct_sizes(torch, N, J, K, M, C):
     """Single frames across the supported grid sizes and the degenerate case,
