@@ -245,8 +245,11 @@ int nlinv_sync(nlinv_plan plan);
  * when plan == NULL).  Never NULL. */
 const char* nlinv_last_error(nlinv_plan plan);
 
-/* Kernel timing for roofline measurement: while enabled, HIP events bracket
- * every launch of kernel class `kernel_id` (NLINV_KT_*) on the plan stream.
+/* Kernel timing for roofline measurement: while enabled, every launch of
+ * kernel class `kernel_id` (NLINV_KT_*) on the plan stream is timed with HIP
+ * events.  The classes of one kernel per launch carry the events in the
+ * kernel's own dispatch (hipExtLaunchKernel), which times the kernel alone;
+ * NLINV_KT_GRID (several kernels) has them recorded around the call.
  * nlinv_timer_read waits for the stream, returns the summed duration (ms) and
  * launch count since the last read, and resets them. */
 enum { NLINV_KT_NONE = 0, NLINV_KT_TOEPLITZ_ROWS = 1, NLINV_KT_COIL_COLS = 2,

@@ -32,6 +32,7 @@ struct nlinv_plan_s {
   int timer_kid = NLINV_KT_NONE;
   std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t ev_used = 0;
+  nlv::LaunchTiming lt;         // armed by timed() for single-kernel classes
   // HIP graphs of nlinv_reconstruct, one per distinct argument set
   bool graphs = false;
   hipStream_t cap_stream = nullptr;
@@ -278,6 +279,20 @@ hipError_t timed(nlinv_plan plan, int kid, F&& f) {
     }
   }
   hipEvent_t a = plan->ev[plan->ev_used], b = plan->ev[plan->ev_used + 1];
+  if (kid != NLINV_KT_GRID) {
+    // one kernel per call: the events ride on its dispatch and time the kernel alone
+    plan->lt.start = a;
+    plan->lt.stop = b;
+    plan->lt.attached = false;
+    const hipError_t he = f();
+    const bool attached = plan->lt.attached;
+    plan->lt.start = plan->lt.stop = nullptr;
+    if (he != hipSuccess) return he;
+    if (!attached) return hipErrorInvalidValue;   // a launcher of this class bypassed launch_timed
+    plan->ev_used += 2;
+    return hipSuccess;
+  }
+  // several kernels per call (gridding): events recorded around the whole call
   hipError_t he = hipEventRecord(a, plan->stream);
   if (he != hipSuccess) return he;
   he = f();
@@ -437,6 +452,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   }
   char* base = static_cast<char*>(d_workspace);
   Bufs& w = plan->w;
+  w.lt = &plan->lt;
   w.tw = reinterpret_cast<double2*>(base + L.tw);
   w.dinv = reinterpret_cast<float*>(base + L.dinv);
   w.P = reinterpret_cast<float*>(base + L.P);

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace nlv {
@@ -43,6 +44,15 @@ struct Shape {
 int grid_jg(int J);
 int grid_nsplit(int B, int J, int R);
 
+// Timing of one launch by the kernel timer: when `start` is set, the next
+// single-kernel launch carries the two events in its own dispatch
+// (hipExtLaunchKernel), so they time the kernel without the cost of
+// separately recorded events, and marks `attached`.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool attached = false;
+};
+
 // Device buffers carved from the caller's workspace.
 struct Bufs {
   double2* tw;    // [G] twiddles (cos, sin)(2 pi m / G)
@@ -69,7 +79,22 @@ struct Bufs {
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
   double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
+  LaunchTiming* lt = nullptr;   // the plan's kernel-timer hook (host memory)
 };
+
+// Launch one kernel; with the timer hook armed, the hook's events are
+// attached to this dispatch.
+template <class... KArgs, class... Args>
+inline hipError_t launch_timed(const Bufs& w, void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shm,
+                               hipStream_t st, Args... args) {
+  if (w.lt && w.lt->start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, w.lt->start, w.lt->stop, 0u, args...);
+    w.lt->attached = true;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+  }
+  return hipGetLastError();
+}
 
 // Grid-size specific launchers (one table per supported G).
 struct GTable {

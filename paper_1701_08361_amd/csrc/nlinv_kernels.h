@@ -738,27 +738,31 @@ struct GLaunch {
   static constexpr int TH_COLS = cols_threads<G>();
 
   static hipError_t coil_rows(const Shape& s, const Bufs& w, hipStream_t st, const float2* src) {
-    k_coil_rows<G, float2><<<s.B * s.NX3, TH_ROW1, 0, st>>>(src, nullptr, nullptr, Partials{},
-                                                                          w.dinv, w.tw, w.U1, s.J, s.X, s.NX3, 0);
-    return hipGetLastError();
+    return launch_timed(w, k_coil_rows<G, float2>, dim3(s.B * s.NX3), dim3(TH_ROW1), 0, st, src,
+                        (const double2*)nullptr, (double2*)nullptr, Partials{}, (const float*)w.dinv,
+                        (const double2*)w.tw, w.U1, s.J, (long long)s.X, s.NX3, 0);
   }
   static hipError_t coil_rows_cg(const Shape& s, const Bufs& w, hipStream_t st, const double2* src,
                                  const double2* rsrc, double2* pdst, Partials sc) {
     constexpr int PER_BLOCK = TH_ROW1 * RHO_PER_THREAD;
     const int nr = rsrc ? (s.R * s.R + PER_BLOCK - 1) / PER_BLOCK : 0;
-    k_coil_rows<G, double2><<<s.B * (s.NX3 + nr), TH_ROW1, 0, st>>>(src, rsrc, pdst, sc, w.dinv,
-                                                                                  w.tw, w.U1, s.J, s.X, s.NX3, nr);
-    return hipGetLastError();
+    return launch_timed(w, k_coil_rows<G, double2>, dim3(s.B * (s.NX3 + nr)), dim3(TH_ROW1), 0, st, src, rsrc,
+                        pdst, sc, (const float*)w.dinv, (const double2*)w.tw, w.U1, s.J, (long long)s.X,
+                        s.NX3, nr);
   }
   template <class S2>
   static hipError_t cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
                                const float2* xh, const double2* pv, void* out) {
     const int blocks = s.B * s.J * s.NT;
     switch (mode) {
-      case 0: k_cols_fwd<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
-      case 1: k_cols_fwd<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
-      case 2: k_cols_fwd<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
-      case 3: k_cols_fwd<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(w.U1, co, xh, pv, w.tw, out, s.J, s.X); break;
+      case 0: return launch_timed(w, k_cols_fwd<G, 0, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+                                   (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
+      case 1: return launch_timed(w, k_cols_fwd<G, 1, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+                                   (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
+      case 2: return launch_timed(w, k_cols_fwd<G, 2, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+                                   (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
+      case 3: return launch_timed(w, k_cols_fwd<G, 3, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+                                   (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -773,8 +777,8 @@ struct GLaunch {
     constexpr int RT = row_lines<G>();
     const int nlines = s.B * s.J * s.G;
     const int blocks = (nlines + RT - 1) / RT;
-    k_toep_rows<G, S2><<<blocks, row_threads<G>(), 0, st>>>(static_cast<S2*>(w.U2), w.P, turns, w.tw, s.J, nlines);
-    return hipGetLastError();
+    return launch_timed(w, k_toep_rows<G, S2>, dim3(blocks), dim3(row_threads<G>()), 0, st, static_cast<S2*>(w.U2),
+                        (const float*)w.P, turns, (const double2*)w.tw, s.J, nlines);
   }
   static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
     return s.fast ? toep_rows_t<float2>(s, w, st, turns) : toep_rows_t<double2>(s, w, st, turns);
@@ -785,10 +789,14 @@ struct GLaunch {
                                 double alpha) {
     const int blocks = s.B * s.J * s.NT;
     switch (mode) {
-      case 0: k_cols_back<G, 0, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
-      case 1: k_cols_back<G, 1, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
-      case 2: k_cols_back<G, 2, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
-      case 3: k_cols_back<G, 3, S2><<<blocks, TH_COLS, 0, st>>>(in, co, xh, z, pv, alpha, w.tw, w.PR, w.U1, w.pq, s.stride, s.J, s.X); break;
+      case 0: return launch_timed(w, k_cols_back<G, 0, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+      case 1: return launch_timed(w, k_cols_back<G, 1, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+      case 2: return launch_timed(w, k_cols_back<G, 2, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+      case 3: return launch_timed(w, k_cols_back<G, 3, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -806,9 +814,15 @@ struct GLaunch {
     double* part = mode == 1 ? w.rr[0] : w.pq;
     const int off = mode == 0 ? s.NY2 : 0;
     switch (mode) {
-      case 0: k_coilh_rows<G, 0><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
-      case 1: k_coilh_rows<G, 1><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
-      case 2: k_coilh_rows<G, 2><<<blocks, TH_ROW1, 0, st>>>(w.U1, w.dinv, w.tw, pv, xh, xprev, alpha, out, out2, part, s.stride, off, s.J, s.X, s.NX3); break;
+      case 0: return launch_timed(w, k_coilh_rows<G, 0>, dim3(blocks), dim3(TH_ROW1), 0, st,
+                                   (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
+                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
+      case 1: return launch_timed(w, k_coilh_rows<G, 1>, dim3(blocks), dim3(TH_ROW1), 0, st,
+                                   (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
+                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
+      case 2: return launch_timed(w, k_coilh_rows<G, 2>, dim3(blocks), dim3(TH_ROW1), 0, st,
+                                   (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
+                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

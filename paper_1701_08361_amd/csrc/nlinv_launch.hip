@@ -423,9 +423,9 @@ hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const f
 hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
                             const double2* p, Partials rr, float2* xh, double alpha) {
   double* next = w.rr[(iter + 1) & 1];
-  k_cg_update<<<s.B * s.NCH, VT, 0, st>>>(w.PR, w.Q, p, w.H, w.Rv, xh, rr, w.pq, s.NY2 + s.NX3,
-                                          alpha, next, iter == 0, last, s.J, s.R * s.R, s.X, s.NCH);
-  return hipGetLastError();
+  return launch_timed(w, k_cg_update, dim3(s.B * s.NCH), dim3(VT), 0, st, (const float2*)w.PR,
+                      (const double2*)w.Q, p, w.H, w.Rv, xh, rr, (const double*)w.pq, s.NY2 + s.NX3, alpha, next,
+                      (int)(iter == 0), last, s.J, s.R * s.R, (long long)s.X, s.NCH);
 }
 
 // Channel compression y[b][j][s] = sum_p cc[j][p] yp[b][p][s]: one thread per
