@@ -184,10 +184,10 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   const nlv::GTable* tab = nlv::table_for(G);
   if (!tab) return bad(NLINV_E_SIZE, "no kernels for this grid size");
   S.NX3 = (S.J * S.GC + tab->row_lines - 1) / tab->row_lines;
-  S.NY2 = S.J * S.NT;
+  S.NRQ = (S.R * S.R + 64 * nlv::RHOQ_E - 1) / (64 * nlv::RHOQ_E);
   S.NCI = (S.R * S.R + nlv::CHUNK - 1) / nlv::CHUNK;
   S.NCH = (int)((S.X + nlv::CHUNK - 1) / nlv::CHUNK);
-  int st = S.NY2 + S.NX3;
+  int st = S.NX3 + S.NRQ;
   if (S.NX3 + S.NCI > st) st = S.NX3 + S.NCI;
   if (S.NCH > st) st = S.NCH;
   S.stride = st;
@@ -594,7 +594,7 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
             }));
     NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-              return plan->t->cols_back(s, w, st, 1, w.U2, w.CO, xh, z, nullptr, 0.0);
+              return plan->t->cols_back(s, w, st, 1, w.U2, w.CO, xh, z);
             }));
     NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
               return plan->t->coilh_rows(s, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
@@ -617,13 +617,13 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
       NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-                return plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr, pc, alpha);
+                return plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
                 return plan->t->coilh_rows(s, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
               }));
       NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
-                return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh, alpha);
+                return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh);
               }));
       nprev = ncur;
       ncur = s.NCH;
@@ -833,7 +833,7 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
   float2* dx = reinterpret_cast<float2*>(d_dx);
   NLV_CHECK(coils_into(plan, xh, w.CO));
   NLV_HIP(plan, nlv::launch_grid(s, w, plan->stream, d_traj, reinterpret_cast<const float2*>(d_dy), w.IMG));
-  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, w.IMG, w.CO, xh, nullptr, nullptr, 0.0));
+  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, w.IMG, w.CO, xh, nullptr));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, xh, nullptr, 0.0, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, dx));
   return NLINV_OK;
@@ -887,7 +887,7 @@ int nlinv_apply_WH(nlinv_plan plan, const nlinv_c64* d_coils, nlinv_c64* d_xhat)
   const Shape& s = plan->s;
   Bufs& w = plan->w;
   const void* c = d_coils;
-  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 3, c, nullptr, nullptr, nullptr, nullptr, 0.0));
+  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 3, c, nullptr, nullptr, nullptr));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, nullptr, nullptr, 0.0, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, reinterpret_cast<float2*>(d_xhat), false));
   return NLINV_OK;
@@ -916,7 +916,7 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
   NLV_HIP(plan, plan->t->coil_rows_cg(s, w, st, pd, nullptr, nullptr, none));
   NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pd, w.U2));
   NLV_HIP(plan, plan->t->toep_rows(s, w, st, turns));
-  NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr, pd, alpha));
+  NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, pd, xh, nullptr, alpha, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, st, pd, alpha, q));
   return NLINV_OK;

@@ -11,6 +11,8 @@ namespace nlv {
 constexpr int ROWS = 8;       // lines per block in the row (x) passes
 constexpr int TW = 8;         // columns per block in the column (y) passes (8 x 16 B = 128 B)
 constexpr int CHUNK = 512;    // vector elements per block in the CG kernels
+constexpr int RHOQ_E = 1;     // rho-block elements per thread of the q_rho blocks of the coil-adjoint rows
+                              // (one: the channel sums of 64 pixels per wave, many short waves)
 constexpr int VT = 256;       // threads per block in the vector / NUDFT kernels
 constexpr int MAXB = 64;      // largest batch (turn table passed by value)
 constexpr int KB_SHORT = 16;  // gridding rows up to this length take one thread
@@ -30,7 +32,7 @@ struct Shape {
   long long X;         // unknowns per item
   int NT;              // column tiles per channel (R / TW)
   int NX3;             // coil row blocks per item (ceil(J * GC / row_lines))
-  int NY2;             // back-column blocks per item (J * NT)
+  int NRQ;             // q_rho blocks per item of the coil-adjoint rows (ceil(R*R / (64 * RHOQ_E)))
   int NCI;             // rho-block chunks (ceil(R*R / CHUNK))
   int NCH;             // vector chunks (ceil(X / CHUNK))
   int stride;          // partial slots per item
@@ -111,13 +113,14 @@ struct GTable {
                          const double2* pv, void* out);
   // row pass: FFT, multiply by the PSF kernel of each item's turn, inverse FFT (in place on U2)
   hipError_t (*toep_rows)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns);
-  // column pass back: mode 0 normal (dot partials to pq), 1 residual (z - T u), 2 adjoint of an
-  // image-space float32 input, 3 plain W^-H column stage of coil images.  Writes U1 (as the
-  // W^-H column stage) and, except in mode 3, PR.
+  // column pass back: mode 0 normal, 1 residual (z - T u), 2 adjoint of an image-space
+  // float32 input, 3 plain W^-H column stage of coil images.  Writes U1 (as the W^-H column
+  // stage) and, except in mode 3, PR.
   hipError_t (*cols_back)(const Shape&, const Bufs&, hipStream_t, int mode, const void* in,
-                          const float2* co, const float2* xh, const float2* z, const double2* pv,
-                          double alpha);
-  // row pass: W^-H along x.  mode 0: q = W^-H(..) + alpha p -> out (pq partials at slot NY2)
+                          const float2* co, const float2* xh, const float2* z);
+  // row pass: W^-H along x.  mode 0: q = W^-H(..) + alpha p -> out, and NRQ further blocks
+  // per item form the image block q_rho = sum_j PR_j + alpha p_rho -> out (pq partials of
+  // Re<p, q>: line blocks at slots [0, NX3), q_rho blocks at [NX3, NX3 + NRQ))
   // mode 1: b = W^-H(..) - alpha (x - xprev) -> out and out2 (rr[0] partials at slot 0)
   // mode 2: raw W^-H -> out.
   hipError_t (*coilh_rows)(const Shape&, const Bufs&, hipStream_t, int mode, const double2* pv,
@@ -138,7 +141,7 @@ const GTable* table_for(int G);
 hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
                           const float2* xprev, double alpha);
 hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
-                            const double2* p, Partials rr, float2* xh, double alpha);
+                            const double2* p, Partials rr, float2* xh);
 // out (float32 [B][X]) = (sum_j PR_j + alpha p ; Q) ; p may be null; without the image
 // block (image_block false) the image part is alpha p, or zero when p is null
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,

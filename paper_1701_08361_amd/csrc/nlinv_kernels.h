@@ -379,16 +379,14 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
 template <int G, int MODE, class S2>
 __global__ void __launch_bounds__(cols_threads<G>())
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
-            const float2* __restrict__ z, const double2* __restrict__ pv, double alpha,
-            const double2* __restrict__ tw, float2* __restrict__ PR, double2* __restrict__ U4,
-            double* __restrict__ part, int stride, int J, long long X) {
+            const float2* __restrict__ z, const double2* __restrict__ tw, float2* __restrict__ PR,
+            double2* __restrict__ U4, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW, NTH = cols_threads<G>();
+  constexpr int R = G / 2, GC = G / 4, NT = R / TW;
   __shared__ C lds[TW * T::LDSC];
-  __shared__ double sh[NTH];
   const bool act = (int)threadIdx.x < TW * T::SIZE;
   const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
-  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
   const int x = tile * TW + col;
   C* L = lds + col * T::LDSC;
   const size_t img = (size_t)bj * R * R;
@@ -409,7 +407,6 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   }
 
   const float2* rho = xh + (size_t)b * X;
-  double dot = 0.0;
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
@@ -422,13 +419,7 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
           s = t;   // plain W^-H of a coil image: no channel products
         } else {
           if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
-          const float2 prf = to_f(cjmul(to_d(co[img + e]), t));
-          PR[img + e] = prf;
-          if constexpr (MODE == 0) {
-            const double2 dr = pv[(size_t)b * X + e];
-            dot += dr.x * prf.x + dr.y * prf.y;
-            if (j == 0) dot += alpha * (dr.x * dr.x + dr.y * dr.y);
-          }
+          PR[img + e] = to_f(cjmul(to_d(co[img + e]), t));
           s = cjmul(to_d(rho[e]), t);
         }
       }
@@ -440,15 +431,13 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
     const int i = coil_idx<G>(n);
     if (i >= 0) o[(size_t)i * R] = val;
   });
-  if constexpr (MODE == 0) {
-    const double s = block_sum_waves<NTH>(dot, sh);
-    if (threadIdx.x == 0) part[(size_t)b * stride + j * NT + tile] = s;
-  }
 }
 
 // ---------------------------------------------------------------------------
 // coilh_rows: W^-H along x plus the regularisation term.
-// MODE 0: q = W^-H(.) + alpha p  (partials Re<p, q> -> part at slot_off)
+// MODE 0: q = W^-H(.) + alpha p  (partials Re<p, q> -> part at slot_off + block);
+//         nr further blocks per item form the image block of q,
+//         q_rho = sum_j PR_j + alpha p_rho (channel sum in channel order, FP64)
 // MODE 1: b = W^-H(.) - alpha (x - x_prev) -> out, out2 (partials |b|^2)
 // MODE 2: raw W^-H(.) -> out
 // ---------------------------------------------------------------------------
@@ -456,14 +445,44 @@ template <int G, int MODE>
 __global__ void __launch_bounds__(row_threads<G>())
 k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
              const double2* __restrict__ pv, const float2* __restrict__ xh, const float2* __restrict__ xprev,
-             double alpha, double2* __restrict__ out, double2* __restrict__ out2,
-             double* __restrict__ part, int stride, int slot_off, int J, long long X, int nb) {
+             const float2* __restrict__ PR, double alpha, double2* __restrict__ out, double2* __restrict__ out2,
+             double* __restrict__ part, int stride, int slot_off, int J, long long X, int nb, int nr) {
   using T = Team<G>;
   constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
+  static_assert(NTH == 64, "the q_rho block count assumes one wavefront per block");
   __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[NTH];
-  // nb blocks per item, each RT of the item's J * GC lines; one partial per block
-  const int b = blockIdx.x / nb, chunk = blockIdx.x - b * nb;
+  // nb line blocks, each RT of the item's J * GC lines, then nr q_rho blocks per
+  // item; one partial per block
+  const int b = blockIdx.x / (nb + nr), chunk = blockIdx.x - b * (nb + nr);
+  if constexpr (MODE == 0) {
+    if (chunk >= nb) {   // block-uniform: image block of q
+      constexpr int E = RHOQ_E;
+      const int e0 = (chunk - nb) * NTH * E + (int)threadIdx.x;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int e = e0 + k * NTH;
+        if (e < R * R) {
+          const size_t ve = (size_t)b * X + e;
+          const double2 p = pv[ve];
+          double qx = 0.0, qy = 0.0;
+          for (int j = 0; j < J; ++j) {
+            const float2 pr = PR[((size_t)b * J + j) * R * R + e];
+            qx += pr.x;
+            qy += pr.y;
+          }
+          qx += alpha * p.x;
+          qy += alpha * p.y;
+          out[ve] = make_double2(qx, qy);
+          acc += p.x * qx + p.y * qy;
+        }
+      }
+      const double s = block_sum_waves<NTH>(acc, sh);
+      if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + chunk] = s;
+      return;
+    }
+  }
   const int rl0 = (int)threadIdx.x / T::SIZE, l0 = chunk * RT + rl0;
   const bool act = rl0 < RT && l0 < J * GC;
   const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
@@ -785,44 +804,46 @@ struct GLaunch {
   }
   template <class S2>
   static hipError_t cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
-                                const float2* co, const float2* xh, const float2* z, const double2* pv,
-                                double alpha) {
+                                const float2* co, const float2* xh, const float2* z) {
     const int blocks = s.B * s.J * s.NT;
     switch (mode) {
       case 0: return launch_timed(w, k_cols_back<G, 0, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
-                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
       case 1: return launch_timed(w, k_cols_back<G, 1, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
-                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
       case 2: return launch_timed(w, k_cols_back<G, 2, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
-                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
       case 3: return launch_timed(w, k_cols_back<G, 3, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
-                                   pv, alpha, (const double2*)w.tw, w.PR, w.U1, w.pq, s.stride, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   static hipError_t cols_back(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
-                              const float2* co, const float2* xh, const float2* z, const double2* pv,
-                              double alpha) {
-    return s.fast ? cols_back_t<float2>(s, w, st, mode, in, co, xh, z, pv, alpha)
-                  : cols_back_t<double2>(s, w, st, mode, in, co, xh, z, pv, alpha);
+                              const float2* co, const float2* xh, const float2* z) {
+    return s.fast ? cols_back_t<float2>(s, w, st, mode, in, co, xh, z)
+                  : cols_back_t<double2>(s, w, st, mode, in, co, xh, z);
   }
   static hipError_t coilh_rows(const Shape& s, const Bufs& w, hipStream_t st, int mode, const double2* pv,
                                const float2* xh, const float2* xprev, double alpha, double2* out,
                                double2* out2) {
-    const int blocks = s.B * s.NX3;
+    const int nr = mode == 0 ? s.NRQ : 0;
+    const int blocks = s.B * (s.NX3 + nr);
     double* part = mode == 1 ? w.rr[0] : w.pq;
-    const int off = mode == 0 ? s.NY2 : 0;
+    const int off = 0;
     switch (mode) {
       case 0: return launch_timed(w, k_coilh_rows<G, 0>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
-                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
+                                   (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
+                                   (long long)s.X, s.NX3, nr);
       case 1: return launch_timed(w, k_coilh_rows<G, 1>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
-                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
+                                   (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
+                                   (long long)s.X, s.NX3, nr);
       case 2: return launch_timed(w, k_coilh_rows<G, 2>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
-                                   alpha, out, out2, part, s.stride, off, s.J, (long long)s.X, s.NX3);
+                                   (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
+                                   (long long)s.X, s.NX3, nr);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -60,16 +60,15 @@ k_cg_init(const float2* __restrict__ PR, const float2* __restrict__ xh, const fl
   if (threadIdx.x == 0) rr0[(size_t)b * stride + slot_off + c] = s;
 }
 
-// CG step: a = rr / Re<p, q>; h += a p; r -= a q; rr' partials.  The image block
-// of q is formed here from the channel partials: q_rho = sum_j PR_j + alpha p_rho.
+// CG step: a = rr / Re<p, q>; h += a p; r -= a q; rr' partials.  q is complete in Q
+// (its image block formed by the q_rho blocks of the coil-adjoint rows).
 // On the last iteration the Newton update x += h is applied instead of the r update.
 // All element loads are issued before the scalar reductions so that their
 // latencies overlap.
 __global__ void __launch_bounds__(VT)
-k_cg_update(const float2* __restrict__ PR, const double2* __restrict__ Q, const double2* __restrict__ P,
-            double2* __restrict__ H, double2* __restrict__ Rv, float2* __restrict__ xh,
-            Partials rr, const double* __restrict__ pq, int npq, double alpha,
-            double* __restrict__ rr_next, int first, int last, int J, int RR, long long X, int nchunk) {
+k_cg_update(const double2* __restrict__ Q, const double2* __restrict__ P, double2* __restrict__ H,
+            double2* __restrict__ Rv, float2* __restrict__ xh, Partials rr, const double* __restrict__ pq,
+            int npq, double* __restrict__ rr_next, int first, int last, long long X, int nchunk) {
   constexpr int EPT = CHUNK / VT;
   __shared__ double sh[VT];
   const int b = blockIdx.x / nchunk, c = blockIdx.x - b * nchunk;
@@ -89,17 +88,7 @@ k_cg_update(const float2* __restrict__ PR, const double2* __restrict__ Q, const 
       xv[k] = xh[ve];
     } else {
       rv[k] = Rv[ve];
-      if (e < RR) {
-        double qx = 0.0, qy = 0.0;
-        for (int j = 0; j < J; ++j) {
-          const float2 pr = PR[((size_t)b * J + j) * RR + e];
-          qx += pr.x;
-          qy += pr.y;
-        }
-        qv[k] = make_double2(qx, qy);
-      } else {
-        qv[k] = Q[ve];
-      }
+      qv[k] = Q[ve];
     }
   }
   const double2 sums = block_sum2_arrays_waves<VT>(pq + (size_t)b * rr.stride, npq,
@@ -116,11 +105,7 @@ k_cg_update(const float2* __restrict__ PR, const double2* __restrict__ Q, const 
     if (last) {
       xh[ve] = make_float2((float)(xv[k].x + hx), (float)(xv[k].y + hy));
     } else {
-      double qx = qv[k].x, qy = qv[k].y;
-      if (e < RR) {
-        qx += alpha * pv[k].x;
-        qy += alpha * pv[k].y;
-      }
+      const double qx = qv[k].x, qy = qv[k].y;
       H[ve] = make_double2(hx, hy);
       const double2 rn = make_double2(rv[k].x - a * qx, rv[k].y - a * qy);
       Rv[ve] = rn;
@@ -421,11 +406,11 @@ hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const f
 }
 
 hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
-                            const double2* p, Partials rr, float2* xh, double alpha) {
+                            const double2* p, Partials rr, float2* xh) {
   double* next = w.rr[(iter + 1) & 1];
-  return launch_timed(w, k_cg_update, dim3(s.B * s.NCH), dim3(VT), 0, st, (const float2*)w.PR,
-                      (const double2*)w.Q, p, w.H, w.Rv, xh, rr, (const double*)w.pq, s.NY2 + s.NX3, alpha, next,
-                      (int)(iter == 0), last, s.J, s.R * s.R, (long long)s.X, s.NCH);
+  return launch_timed(w, k_cg_update, dim3(s.B * s.NCH), dim3(VT), 0, st, (const double2*)w.Q, p, w.H, w.Rv,
+                      xh, rr, (const double*)w.pq, s.NX3 + s.NRQ, next, (int)(iter == 0), last,
+                      (long long)s.X, s.NCH);
 }
 
 // Channel compression y[b][j][s] = sum_p cc[j][p] yp[b][p][s]: one thread per
