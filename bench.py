@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import multiprocessing as mp
 import os
@@ -42,11 +43,19 @@ KERNEL_SOURCES = ["paper_1701_08361_amd/csrc/nlinv_fft.h", "paper_1701_08361_amd
                   "paper_1701_08361_amd/csrc/nlinv_internal.h"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace collapsed, so that the
+    hash follows the code the counters measured and not its comments."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -8,12 +8,14 @@
 //     q_rho = sum_j conj(c_j) t_j + alpha d_rho,   q_c_hat_j = W^-H(conj(rho) t_j) + alpha d_c_hat_j
 // with every 2D FFT split into a row (x) and a column (y) pass and the
 // pointwise steps fused into the pass that holds the data in registers:
-//     coil_rows : x-iFFT of the (weighted) coil spectra            G_c rows  -> U1
+//     coil_rows : direction update p = r + beta p, x-iFFT of the
+//                 (weighted) coil spectra                           G_c rows  -> U1
 //     cols_fwd  : y-iFFT -> u_j -> y-FFT                            R columns -> U2
 //     toep_rows : x-FFT -> x P -> x-iFFT (in place)                 G rows
 //     cols_back : y-iFFT -> conj(c_j) t_j, conj(rho) t_j -> y-FFT   R columns -> PR, U1
-//     coilh_rows: x-FFT -> x weight (+ alpha p), dot partials       G_c rows
-//     cg_update : channel sum, CG scalars, h and r updates
+//     coilh_rows: x-FFT -> x weight (+ alpha p); channel sum of the
+//                 image block; <p, q> partials                     G_c rows, R^2 pixels -> Q
+//     cg_update : CG scalars, h and r updates
 // Zero padding and cropping are never materialised: absent inputs are not
 // loaded and unwanted outputs are not stored.
 //
