@@ -549,8 +549,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(sharding across GPUs is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (independent slices or series would shard "
+                                   "one per GPU; no multi-GPU path is built)"}))
         sys.exit(2)
 
     frames_plain = max(U, min(100, args.warmup + args.steps + args.kt_frames))
