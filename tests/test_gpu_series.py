@@ -153,3 +153,42 @@ def test_frames_argument_errors(torch):
         plan.set_batch(3)
     assert ei.value.code == N.E_ARG
     assert plan.B == 2
+
+
+def test_uneven_channel_counts_share_a_batch(torch):
+    """Series with fewer coils join a batched plan of more channels with their
+    missing channels zero: a channel with zero data and a zero coil spectrum
+    keeps a zero residual, right-hand side, CG direction and update, so it
+    stays exactly zero and only appends exact zeros to every channel sum and
+    partial-sum array (the real channels' block assignment and summation
+    order do not change).  So the padded item equals its own smaller plan bit
+    for bit, and the full item its batch-1 plan."""
+    N, K, U, M, C = 32, 5, 2, 3, 6
+    Ja, Jb = 6, 10
+    print_case("uneven channels", N=N, Ja=Ja, Jb=Jb, K=K, M=M, C=C)
+    sa = synth.real_time_series(seed=27, N=N, J=Ja, J_phys=8, K=K, U=U, frames=2)
+    sb = synth.real_time_series(seed=28, N=N, J=Jb, J_phys=12, K=K, U=U, frames=2)
+    pa = nl().Plan(N, Ja, K, U=U, newton=M, cg=C)
+    pb = nl().Plan(N, Jb, K, U=U, newton=M, cg=C)
+    both = nl().Plan(N, Jb, K, U=U, batch=2, newton=M, cg=C)
+    za = [pa.grid(dev(torch, sa.traj[f:f + 1]), dev(torch, sa.y[f:f + 1]), turns=[int(sa.turn[f])]) for f in range(2)]
+    zb = [pb.grid(dev(torch, sb.traj[f:f + 1]), dev(torch, sb.y[f:f + 1]), turns=[int(sb.turn[f])]) for f in range(2)]
+    for t in range(U):                 # the batch plan needs the turns' PSF kernels
+        both.psf(dev(torch, sa.traj[t]), t)
+    assert [int(t) for t in sa.turn[:2]] == [int(t) for t in sb.turn[:2]]
+    R2, gc2 = N * N, both.Gc * both.Gc
+    assert both.X == R2 + Jb * gc2
+    xa = xb = x2 = None
+    for f in range(2):
+        ts = [int(sa.turn[f])]
+        xa, ia, _ = pa.reconstruct(za[f], ts, xprev=xa, init=1 if f == 0 else 2, want_img=True)
+        xb, ib, _ = pb.reconstruct(zb[f], ts, xprev=xb, init=1 if f == 0 else 2, want_img=True)
+        z2 = torch.zeros(2, Jb, N, N, dtype=torch.complex64, device="cuda")
+        z2[0, :Ja] = za[f][0]
+        z2[1] = zb[f][0]
+        x2, i2, _ = both.reconstruct(z2, ts * 2, xprev=x2, init=1 if f == 0 else 2, want_img=True)
+        # the padded item: its extra coil blocks stay exactly zero
+        assert torch.count_nonzero(x2[0, R2 + Ja * gc2:]) == 0
+        assert torch.equal(x2[0, :R2 + Ja * gc2], xa[0]) and torch.equal(i2[0], ia[0]), f
+        # the full item is untouched by its neighbour
+        assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0])
