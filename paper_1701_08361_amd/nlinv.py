@@ -137,21 +137,30 @@ class Plan:
         self.Bmax = self.params.batch
         self.U = self.params.U
         self.S_r = self.S // K
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("plans live on a GPU (device 'cuda' or 'cuda:k')")
+        # the plan belongs to one device: resolve "cuda" to the current index
+        self.device = torch.device("cuda", torch.cuda.current_device() if dev.index is None else dev.index)
         nbytes = workspace_size(self.params)
         self.ws_bytes = nbytes
-        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-raw.data_ptr()) % 256
-        self._raw = raw
-        self.ws = raw[off:off + nbytes]
-        self._stream = torch.cuda.current_stream(self.device).cuda_stream
-        h = _P()
-        _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
-                                          _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
+        with torch.cuda.device(self.device):    # the library creates the plan on the current device
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            self._raw = raw
+            self.ws = raw[off:off + nbytes]
+            self._stream = torch.cuda.current_stream(self.device).cuda_stream
+            h = _P()
+            _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
+                                              _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
         self.handle = h
 
     # -- helpers ---------------------------------------------------------
     def _stream_sync(self):
+        cur = self.torch.cuda.current_device()
+        if cur != self.device.index:
+            raise RuntimeError(f"the plan lives on {self.device} but cuda:{cur} is current; "
+                               f"call it inside torch.cuda.device({self.device.index})")
         s = self.torch.cuda.current_stream(self.device).cuda_stream
         if s != self._stream:
             _check(self.lib.nlinv_set_stream(self.handle, _P(s)), self.handle)
@@ -162,8 +171,8 @@ class Plan:
             if allow_none:
                 return None
             raise ValueError(f"{name} is required")
-        if t.device != self.device and not (t.is_cuda and self.device.type == "cuda"):
-            raise ValueError(f"{name} must be on {self.device}")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
         if t.dtype != dtype:
             raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
         if not t.is_contiguous():
@@ -367,7 +376,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "handle", None):
-            self.lib.nlinv_plan_destroy(self.handle)
+            with self.torch.cuda.device(self.device):
+                self.lib.nlinv_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

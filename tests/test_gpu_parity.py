@@ -314,6 +314,16 @@ def test_state_and_argument_errors(torch):
     with pytest.raises(N.NlinvError) as ei:
         plan.reconstruct(z, [0], xprev=x, xhat=x, init=2)   # aliasing
     assert ei.value.code == N.E_ARG
+    # the binding checks tensors before any library call: device, dtype, shape
+    assert plan.device == torch.device("cuda", torch.cuda.current_device())
+    with pytest.raises(ValueError):
+        plan.reconstruct(z.cpu(), [0], init=1)
+    with pytest.raises(TypeError):
+        plan.reconstruct(z.to(torch.complex128), [0], init=1)
+    with pytest.raises(ValueError):
+        plan.reconstruct(z[:, :2].contiguous(), [0], init=1)
+    with pytest.raises(ValueError):
+        N.Plan(32, 3, 5, device="cpu")
 
 
 # ---------------------------------------------------------------------------
