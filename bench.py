@@ -505,8 +505,19 @@ def cpu_baseline(seconds_hint: float = 30.0):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": f"1 frame (frame 0 of the 160px 10ch series: exact gridding, PSF kernel, "
-                      f"7x20 IRGNM) in {dt:.1f} s on {os.cpu_count()} host CPUs "
-                      f"({platform.processor() or platform.machine()})"}
+                      f"7x20 IRGNM) in {dt:.1f} s, {threads} BLAS threads on {os.cpu_count()} host CPUs "
+                      f"({cpu_model()})"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def main():
