@@ -319,7 +319,6 @@ int turns_of(nlinv_plan plan, const int32_t* h_turn, nlv::TurnArgs* t) {
 // c_j = W^-1 c_hat_j of `xh` into `co`.
 int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
   const Shape& s = plan->s;
-  const Partials none{};
   NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, plan->w, plan->stream, xh); }));
   NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
             return plan->t->cols_fwd(s, plan->w, plan->stream, 0, co, xh, nullptr, nullptr);
@@ -579,7 +578,6 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   const Shape& s = plan->s;
   Bufs& w = plan->w;
   hipStream_t st = plan->stream;
-  const Partials none{};
 
   if (init == 1) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, nullptr, 1));
   if (init == 2) NLV_HIP(plan, nlv::launch_init_x(s, st, xh, xp, 2));
@@ -793,7 +791,6 @@ int nlinv_apply_F(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xhat,
   const Shape& s = plan->s;
   Bufs& w = plan->w;
   const float2* xh = reinterpret_cast<const float2*>(d_xhat);
-  const Partials none{};
   NLV_HIP(plan, plan->t->coil_rows(s, w, plan->stream, xh));
   NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 2, w.CO, xh, nullptr, w.IMG));
   NLV_HIP(plan, nlv::launch_nudft_fwd(s, plan->stream, d_traj, w.IMG, reinterpret_cast<float2*>(d_y)));
