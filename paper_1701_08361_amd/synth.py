@@ -22,7 +22,10 @@ model is used to make the data.
 
 Channel compression (paper, Sec. 3.1, preprocessing stage): the physical
 channels are compressed to J virtual channels with a PCA computed on the first
-frame (the calibration phase) and applied to every frame.
+frame (the calibration phase) and applied to every frame.  This only prepares
+the virtual-channel inputs of the reconstruction tests (numpy's SVD).  The
+library's compression and the oracle's are checked against each other on the
+receive channels returned with compress=False, never against this function.
 
 Scaling and noise: each series is scaled by 100/||y_0|| (frame 0, all
 channels), then complex Gaussian noise of standard deviation sigma
