@@ -128,6 +128,17 @@ int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn);
 /* (also builds the turn's gridding table; copies d_traj to the host and
  * blocks until the table is in the workspace) */
 
+/* The same for a turn acquired with fewer spokes than the plan's K: only the
+ * first `spokes` spokes of d_traj [K][S_r][2] count (1 <= spokes <= K,
+ * NLINV_E_ARG otherwise); the PSF kernel and the gridding table of `turn`
+ * are built from those samples alone, so a series with fewer spokes can
+ * share a batched plan.  Its data keep the plan's layout [J][K * S_r] with
+ * the spokes beyond `spokes` never read by the table-based gridding
+ * (nlinv_grid with turns); the exact sum (no turns, or NLINV_F_EXACT_GRID)
+ * reads every sample, so there those samples must be zero.
+ * nlinv_psf(plan, d_traj, turn) is nlinv_psf_spokes(plan, d_traj, K, turn). */
+int nlinv_psf_spokes(nlinv_plan plan, const float* d_traj, int32_t spokes, int32_t turn);
+
 /* Gridding (Sec. 3.1, preprocessing): z_j = F^H y_j on the R x R field of view,
  * z_j(r) = (1/R) sum_s y_{j,s} exp(+i 2 pi k_s . r).
  * d_traj [B][K][S_r][2], d_y [B][J][S] -> d_z [B][J][R][R].

@@ -332,17 +332,18 @@ int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
 // PSF kernel and (if enabled) Kaiser-Bessel gridding table of one turn from
 // its trajectory (device, [K][S_r][2]).  The table is built on the host, so
 // this waits for the trajectory copy and the upload.
-int build_turn(nlinv_plan plan, const float* d_traj, int turn) {
+// PSF kernel and gridding table of `turn` from its first S samples (S <= s.S).
+int build_turn(nlinv_plan plan, const float* d_traj, int turn, int S) {
   const Shape& s = plan->s;
-  NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj, turn));
+  NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj, S, turn));
   if (s.kb) {
-    std::vector<float> traj((size_t)s.S * 2);
+    std::vector<float> traj((size_t)S * 2);
     NLV_HIP(plan, hipMemcpyAsync(traj.data(), d_traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost,
                                  plan->stream));
     NLV_HIP(plan, hipStreamSynchronize(plan->stream));
     std::vector<int> rp;
     std::vector<int2> ent;
-    kb_table(traj.data(), s.S, s.G, rp, ent);
+    kb_table(traj.data(), S, s.G, rp, ent);
     if ((long long)ent.size() > s.kbe_stride) return fail(plan, NLINV_E_SIZE, "gridding table overflow");
     // grid points by row length: short rows (one thread each) from the front,
     // long rows (one wavefront each) from the back
@@ -535,9 +536,15 @@ int nlinv_set_stream(nlinv_plan plan, void* stream) {
 
 int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn) {
   NLV_CHECK(check_plan(plan));
+  return nlinv_psf_spokes(plan, d_traj, plan->p.K, turn);
+}
+
+int nlinv_psf_spokes(nlinv_plan plan, const float* d_traj, int32_t spokes, int32_t turn) {
+  NLV_CHECK(check_plan(plan));
   NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
   if (turn < 0 || turn >= plan->s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
-  return build_turn(plan, d_traj, turn);
+  if (spokes < 1 || spokes > plan->p.K) return fail(plan, NLINV_E_ARG, "spokes must be in [1, K]");
+  return build_turn(plan, d_traj, turn, (int)((long long)spokes * (plan->s.S / plan->p.K)));
 }
 
 int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const int32_t* h_turn,
@@ -553,7 +560,7 @@ int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const
     for (int b = 0; b < s.B; ++b) {
       const int t = h_turn[b];
       if (plan->psf_valid[t]) continue;
-      NLV_CHECK(build_turn(plan, d_traj + (size_t)b * s.S * 2, t));
+      NLV_CHECK(build_turn(plan, d_traj + (size_t)b * s.S * 2, t, (int)s.S));
     }
     if (s.kb) {
       nlv::TurnArgs turns;

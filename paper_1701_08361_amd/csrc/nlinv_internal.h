@@ -154,7 +154,8 @@ hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const floa
                        float2* z);
 hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
                             float2* y);
-hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int turn);
+// PSF kernel of `turn` from the first S samples of traj (S <= s.S)
+hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn);
 // channel compression y [B][J][S] = cc [J][Jp] x yp [B][Jp][S]; covariance of one frame [Jp][S]
 constexpr int MAX_JP = 128;
 hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y);

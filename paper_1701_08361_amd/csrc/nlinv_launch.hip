@@ -549,11 +549,11 @@ hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, c
   return hipGetLastError();
 }
 
-hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int turn) {
+hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn) {
   const GTable* t = table_for(s.G);
-  if (!t) return hipErrorInvalidValue;
+  if (!t || S < 1 || S > s.S) return hipErrorInvalidValue;
   const int nt = (s.G / GT) * (s.G / GT);
-  k_psf_lags<<<nt, VT, 0, st>>>(traj, w.psf, s.S, s.R, s.G);
+  k_psf_lags<<<nt, VT, 0, st>>>(traj, w.psf, S, s.R, s.G);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // F^H F = (1/R^2) psf-convolution; the unnormalised 2D DFT pair contributes 1/G^2

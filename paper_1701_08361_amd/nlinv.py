@@ -56,6 +56,7 @@ def load() -> ctypes.CDLL:
         "nlinv_plan_destroy": [_P],
         "nlinv_set_stream": [_P, _P],
         "nlinv_psf": [_P, _P, _I],
+        "nlinv_psf_spokes": [_P, _P, _I, _I],
         "nlinv_grid": [_P, _P, _P, _P, _P],
         "nlinv_reconstruct": [_P, _P, _P, _P, _P, _I, _P, _P],
         "nlinv_reconstruct_frames": [_P, _I, _P, _P, _P, _P, _P, _P],
@@ -197,11 +198,16 @@ class Plan:
         return self.torch.empty(*shape, dtype=dtype or self.torch.complex64, device=self.device)
 
     # -- API -------------------------------------------------------------
-    def psf(self, traj, turn: int):
+    def psf(self, traj, turn: int, spokes: Optional[int] = None):
+        """PSF kernel and gridding table of `turn` from traj [K][S_r][2]; with
+        `spokes`, from its first `spokes` spokes only (nlinv_psf_spokes)."""
         torch = self.torch
         self._t(traj, torch.float32, (self.K, self.S_r, 2), "traj")
         self._stream_sync()
-        _check(self.lib.nlinv_psf(self.handle, self._ptr(traj), int(turn)), self.handle)
+        if spokes is None:
+            _check(self.lib.nlinv_psf(self.handle, self._ptr(traj), int(turn)), self.handle)
+        else:
+            _check(self.lib.nlinv_psf_spokes(self.handle, self._ptr(traj), int(spokes), int(turn)), self.handle)
 
     def grid(self, traj, y, turns: Optional[Sequence[int]] = None, z=None):
         torch = self.torch

@@ -86,5 +86,7 @@ def test_null_plan_rejected(lib):
     assert lib.nlinv_plan_destroy(None) == nl.E_ARG
     assert lib.nlinv_reconstruct_frames(None, 1, None, None, None, None, None, None) == nl.E_ARG
     assert lib.nlinv_set_batch(None, 1) == nl.E_ARG
+    assert lib.nlinv_psf(None, None, 0) == nl.E_ARG
+    assert lib.nlinv_psf_spokes(None, None, 1, 0) == nl.E_ARG
     assert lib.nlinv_get_batch(None) == 0
     assert b"NULL" in lib.nlinv_last_error(None)

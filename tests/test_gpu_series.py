@@ -192,3 +192,45 @@ def test_uneven_channel_counts_share_a_batch(torch):
         assert torch.equal(x2[0, :R2 + Ja * gc2], xa[0]) and torch.equal(i2[0], ia[0]), f
         # the full item is untouched by its neighbour
         assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0])
+
+
+def test_uneven_spoke_counts_share_a_batch(torch):
+    """A turn declared with fewer spokes (nlinv_psf_spokes) builds its PSF
+    kernel and gridding table from those spokes alone; a series with 9
+    spokes per frame then runs in a 15-spoke batched plan, its data padded
+    with spokes that are never read, and equals its own 9-spoke plan bit for
+    bit, while the 15-spoke item equals its batch-1 plan."""
+    N, J, U, M, C = 32, 4, 2, 3, 5
+    Ka, Kb = 9, 15
+    print_case("uneven spokes", N=N, J=J, Ka=Ka, Kb=Kb, M=M, C=C)
+    sa = synth.real_time_series(seed=41, N=N, J=J, J_phys=6, K=Ka, U=U, frames=2)
+    sb = synth.real_time_series(seed=42, N=N, J=J, J_phys=6, K=Kb, U=U, frames=2)
+    Sr = 2 * N
+    pa = nl().Plan(N, J, Ka, U=U, newton=M, cg=C)
+    pb = nl().Plan(N, J, Kb, U=U, newton=M, cg=C)
+    both = nl().Plan(N, J, Kb, U=2 * U, batch=2, newton=M, cg=C)   # turns 0..U-1: a, U..2U-1: b
+    # a's trajectories and data padded to Kb spokes (zeros, never read)
+    ta = np.zeros((2, Kb, Sr, 2), np.float32)
+    ta[:, :Ka] = sa.traj
+    ya = np.zeros((2, J, Kb * Sr), np.complex64)
+    ya[:, :, :Ka * Sr] = sa.y
+    for t in range(U):
+        both.psf(dev(torch, ta[t]), t, spokes=Ka)
+        both.psf(dev(torch, sb.traj[t]), U + t)
+    with pytest.raises(nl().NlinvError):
+        both.psf(dev(torch, ta[0]), 0, spokes=Kb + 1)
+    xa = xb = x2 = None
+    for f in range(2):
+        t = int(sa.turn[f])
+        assert t == int(sb.turn[f])
+        za = pa.grid(dev(torch, sa.traj[f:f + 1]), dev(torch, sa.y[f:f + 1]), turns=[t])
+        zb = pb.grid(dev(torch, sb.traj[f:f + 1]), dev(torch, sb.y[f:f + 1]), turns=[t])
+        traj2 = dev(torch, np.stack([ta[f], sb.traj[f]]))
+        y2 = dev(torch, np.stack([ya[f], sb.y[f]]))
+        z2 = both.grid(traj2, y2, turns=[t, U + t])
+        assert torch.equal(z2[0], za[0]) and torch.equal(z2[1], zb[0])
+        xa, ia, _ = pa.reconstruct(za, [t], xprev=xa, init=1 if f == 0 else 2, want_img=True)
+        xb, ib, _ = pb.reconstruct(zb, [t], xprev=xb, init=1 if f == 0 else 2, want_img=True)
+        x2, i2, _ = both.reconstruct(z2, [t, U + t], xprev=x2, init=1 if f == 0 else 2, want_img=True)
+        assert torch.equal(x2[0], xa[0]) and torch.equal(i2[0], ia[0]), f
+        assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0]), f
