@@ -433,6 +433,25 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
             "by_frames": rows}
 
 
+def run_grid_choice(torch, nl, reps):
+    """The grid-size lookup table of this GPU (G -> device time of one
+    normal-operator application at batch 1, 10 channels, 15 spokes) over every
+    grid side the library supports, and the grid it picks (gamma >= 1.4) for
+    the image sides of Table oversampling_ratio."""
+    from paper_1701_08361_amd import gridsize as GS
+    grids = GS.supported_grids(nl)
+    lut = GS.measure(nl, torch, grids, J=J, K=K, reps=reps)
+    choice = {}
+    for n in (128, 144, 160, 170, 256):
+        try:
+            g = GS.choose(n, lut)
+            choice[str(n)] = {"G": g, "gamma": round(GS.gamma(n, g), 5)}
+        except ValueError:
+            choice[str(n)] = None
+    return {"us_per_normal_application": {str(g): round(t, 2) for g, t in lut.items()},
+            "J": J, "K": K, "reps": reps, "choice_gamma_min_1_4": choice}
+
+
 def run_pipeline(torch, raw, periods, period_ms, shared, graphs):
     """Slices of SLICES streamed through paper_1701_08361_amd.serve.Server at
     1000 / period_ms frames/s each: receive-channel samples in pinned host
@@ -554,6 +573,8 @@ def main():
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
     ap.add_argument("--autotune-frames", default="5,10,25,50",
                     help="series lengths of the autotuning run (learning mode over all settings; '' = skip)")
+    ap.add_argument("--grid-lut-reps", type=int, default=30,
+                    help="applications timed per grid side for the grid-size lookup table (0 = skip)")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -707,6 +728,8 @@ def main():
     if plain_data is not None and args.autotune_frames and not args.fast:
         out["autotune"] = run_autotune(torch, nl, plain_data, [int(f) for f in args.autotune_frames.split(",")],
                                        not args.no_graphs)
+    if args.grid_lut_reps > 0 and not args.fast:
+        out["grid_choice"] = run_grid_choice(torch, nl, args.grid_lut_reps)
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],

@@ -12,10 +12,14 @@
  *
  * Conventions shared by every call
  * --------------------------------
- *  - Sizes: G = grid side (2N unless given), R = G/2 reconstructed side
- *    (= N), G_c = G/4 coil-spectrum side (Sec. 3.2, coil cropping),
+ *  - Sizes: G = grid side = 2 gamma N with 1 <= gamma <= 2 (Sec. 3.2,
+ *    grid oversampling; 2N unless given), R = G/2 reconstructed side,
+ *    G_c = G/4 coil-spectrum side (Sec. 3.2, coil cropping),
  *    S = K * S_r samples per channel, X = R*R + J*G_c*G_c unknowns.
- *    Supported grids: G = 2N in {64, 128, 256, 320, 384, 448}.
+ *    Supported grids: G in {64, 128, 256, 320, 384, 448} with 2N <= G <= 4N.
+ *    Every array is on the R x R field of view; for gamma > 1 the N x N
+ *    output image is its centre, rows and columns R/2 - floor(N/2) to
+ *    R/2 + ceil(N/2) - 1.
  *  - complex64 is interleaved (re, im) float32 (nlinv_c64).
  *  - Images are R x R row-major [y][x]; pixel (0,0) sits at (x, y) =
  *    (-R/2, -R/2) pixels.  The unknown x_hat = W x is stored as the image rho
@@ -83,7 +87,7 @@ enum { NLINV_F_FAST = 1, NLINV_F_EXACT_GRID = 2 };
 /* Plan parameters.  nlinv_params_default fills the defaults noted here. */
 typedef struct {
   int32_t N;          /* image side (required)                                  */
-  int32_t G;          /* grid side; 0 -> 2N (Sec. 3.2, G = 2 gamma N, gamma = 1)  */
+  int32_t G;          /* grid side 2 gamma N, 2N..4N; 0 -> 2N (gamma = 1)       */
   int32_t J;          /* channels (virtual coils), 1..64                         */
   int32_t K;          /* spokes per frame, odd                                   */
   int32_t S_r;        /* samples per spoke; 0 -> 2N                              */

@@ -175,9 +175,9 @@ def run_series(nl, torch, traj, y, turns, config: Dict, newton: int, cg: int, U:
         for t in range(min(U, F)):
             plan.psf(traj[t].contiguous(), int(turns[t]))
         dev = y.device
-        z = torch.empty(T, J, N, N, dtype=torch.complex64, device=dev)
+        z = torch.empty(T, J, plan.R, plan.R, dtype=torch.complex64, device=dev)
         xb = [torch.empty(T, plan.X, dtype=torch.complex64, device=dev) for _ in range(2)]
-        img = torch.empty(T, N, N, dtype=torch.float32, device=dev)
+        img = torch.empty(T, plan.R, plan.R, dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prev, par, n = None, 0, 0

@@ -152,8 +152,10 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   auto bad = [&](int code, const char* m) { *err = m; return code; };
   if (!p) return bad(NLINV_E_ARG, "params is NULL");
   if (p->N <= 0) return bad(NLINV_E_ARG, "N must be positive");
+  // G = 2 gamma N with 1 <= gamma <= 2 (Sec. 3.2): the reconstructed field of
+  // view R = G/2 holds the N x N image in its centre
   const int G = p->G == 0 ? 2 * p->N : p->G;
-  if (G != 2 * p->N) return bad(NLINV_E_SIZE, "only G = 2N is supported");
+  if (G < 2 * p->N || G > 4 * p->N) return bad(NLINV_E_SIZE, "G must be in [2N, 4N] (G = 2 gamma N, 1 <= gamma <= 2)");
   if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384 or 448");
   if (p->J < 1 || p->J > 64) return bad(NLINV_E_ARG, "J must be in [1, 64]");
   if (p->K < 1 || (p->K % 2) == 0) return bad(NLINV_E_ARG, "K must be a positive odd number");

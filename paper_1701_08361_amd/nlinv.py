@@ -377,6 +377,12 @@ class Plan:
         _check(self.lib.nlinv_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n)), self.handle)
         return ms.value, n.value
 
+    def crop(self, img):
+        """The N x N output image: the centre of an [..., R, R] array (rows and
+        columns R/2 - floor(N/2) to R/2 + ceil(N/2) - 1; all of it when G = 2N)."""
+        o = self.R // 2 - self.N // 2
+        return img[..., o:o + self.N, o:o + self.N]
+
     def sync(self):
         _check(self.lib.nlinv_sync(self.handle), self.handle)
 

@@ -44,7 +44,8 @@ def test_workspace_grows_with_batch(lib):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(N=100, J=8, K=13), nl.E_SIZE),           # G = 200 unsupported
-    (dict(N=64, J=8, K=13, G=192), nl.E_SIZE),     # gamma != 1
+    (dict(N=64, J=8, K=13, G=192), nl.E_SIZE),     # gamma 1.5, but no kernels for G = 192
+    (dict(N=64, J=8, K=13, G=64), nl.E_SIZE),      # gamma < 1
     (dict(N=64, J=8, K=14), nl.E_ARG),             # even spoke count
     (dict(N=64, J=0, K=13), nl.E_ARG),
     (dict(N=64, J=65, K=13), nl.E_ARG),

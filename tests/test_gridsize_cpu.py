@@ -1,0 +1,101 @@
+"""Grid-size choice (Sec. 3.2, computational cost reduction; Table
+oversampling_ratio): the rule G = 2 gamma N with gamma in [1.4, 2], the
+fastest measured grid, the lookup-table file, and the C-ABI's acceptance of
+gamma > 1.  Host-only: no kernel runs."""
+import os
+
+import pytest
+
+from paper_1701_08361_amd import gridsize as GS
+from paper_1701_08361_amd import nlinv as nl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nl.LIB_PATH):
+        from paper_1701_08361_amd import build
+        build.build(verbose=False)
+    return nl.load()
+
+
+def _printed_rows():
+    rows = []
+    with open(os.path.join(HERE, "golden", "grid_sizes.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                n, gf, gam, g, _, _ = line.split()
+                rows.append((int(n), int(gf), float(gam), int(g)))
+    return rows
+
+
+def test_supported_grids_come_from_the_library(lib):
+    assert GS.supported_grids(nl) == [64, 128, 256, 320, 384, 448]
+
+
+@pytest.mark.parametrize("N,G,expect", [
+    (160, 448, dict(R=224, G=448, Gc=112, S=15 * 320, X=224 * 224 + 10 * 112 * 112)),   # gamma 1.4
+    (128, 384, dict(R=192, G=384, Gc=96, S=15 * 256, X=192 * 192 + 10 * 96 * 96)),      # gamma 1.5
+    (32, 128, dict(R=64, G=128, Gc=32, S=15 * 64, X=64 * 64 + 10 * 32 * 32)),           # gamma 2
+])
+def test_abi_takes_gamma_above_one(lib, N, G, expect):
+    """R = G/2 widens the field of view; the readout keeps 2N samples."""
+    assert nl.sizes(nl.make_params(N, 10, 15, G=G)) == expect
+
+
+@pytest.mark.parametrize("N,G", [(64, 64), (160, 256), (32, 256), (100, 448)])
+def test_abi_rejects_gamma_outside_one_to_two(lib, N, G):
+    with pytest.raises(nl.NlinvError) as ei:
+        nl.workspace_size(nl.make_params(N, 4, 5, G=G))
+    assert ei.value.code == nl.E_SIZE
+    assert b"gamma" in lib.nlinv_last_error(None)
+
+
+def test_printed_choices_obey_the_rule():
+    """Every optimal grid of Table oversampling_ratio has gamma >= 1.4 and is
+    admissible for its N, and so is the fixed gamma = 1.5 grid."""
+    for N, G_fixed, gamma, G in _printed_rows():
+        assert gamma >= GS.GAMMA_MIN
+        assert GS.admissible(N, [G, G_fixed]) == sorted([G, G_fixed])
+
+
+def test_choose_takes_the_fastest_admissible_grid():
+    lut = {320: 30.0, 384: 20.0, 448: 25.0, 512: 10.0}
+    # N = 160: 448 <= G <= 640
+    assert GS.choose(160, lut) == 512
+    assert GS.admissible(160, lut) == [448, 512]
+    # N = 128: 358.4 <= G <= 512; 512 is fastest
+    assert GS.choose(128, lut) == 512
+    # gamma_max = 1.5 keeps 512 out for N = 128
+    assert GS.choose(128, lut, gamma_max=1.5) == 384
+    # equal times: the smaller grid
+    assert GS.choose(128, {384: 5.0, 448: 5.0}) == 384
+    # gamma_min = 1 admits G = 2N
+    assert GS.choose(160, {320: 1.0, 448: 2.0}, gamma_min=1.0) == 320
+    assert GS.gamma(160, 448) == 1.4
+
+
+def test_choose_without_admissible_grid_raises():
+    with pytest.raises(ValueError):
+        GS.choose(256, {320: 1.0, 448: 1.0})       # needs G >= 716.8
+    with pytest.raises(ValueError):
+        GS.admissible(100, [256], gamma_min=0.5)
+    with pytest.raises(ValueError):
+        GS.admissible(0, [256])
+
+
+def test_lookup_table_file_round_trip(tmp_path):
+    path = str(tmp_path / "grids.json")
+    db = GS.GridLUT(path)
+    key = GS.GridLUT.key("gfx950", "abc", 10)
+    assert db.get(key) is None
+    db.store(key, {448: 41.5, 320: 22.0})
+    again = GS.GridLUT(path)
+    assert again.get(key) == {448: 41.5, 320: 22.0}
+    assert GS.choose(160, again.get(key)) == 448
+    with pytest.raises(ValueError):
+        db.store(key, {448: 0.0})
+    with pytest.raises(ValueError):
+        db.store(key, {448: float("nan")})

@@ -139,6 +139,24 @@ def test_cartesian_full_coverage_gives_scaled_identity():
     assert rel(O.toeplitz(u, P), u) < 1e-12
 
 
+def test_wider_field_of_view_keeps_pixel_positions():
+    """gamma > 1 (Sec. 3.2): G = 2 gamma N widens the reconstructed field of
+    view to R' = G/2 > N around the same pixels.  The image padded into the
+    wider FOV gives the same samples, up to the unitary scale 1/R; gridding
+    onto the wider FOV holds the narrow one in its centre; the PSF of the
+    narrow FOV is the centre of the wide one (all up to that scale)."""
+    N, Rw, K = 8, 12, 5
+    traj = synth.radial_trajectory(N, K, 2 * N, 0, 1).astype(np.float64)
+    rng = np.random.default_rng(7)
+    u = crand(rng, N, N)
+    assert rel(Rw * O.nudft(O.pad(u, Rw), traj), N * O.nudft(u, traj)) < 1e-12
+    y = crand(rng, 2, traj.size // 2)
+    assert rel(Rw * O.crop(O.grid(y, traj, Rw), N), N * O.grid(y, traj, N)) < 1e-12
+    o = Rw - N
+    wide = O.psf_lags(traj, Rw)[o:o + 2 * N - 1, o:o + 2 * N - 1]
+    assert rel(Rw ** 2 * wide, N ** 2 * O.psf_lags(traj, N)) < 1e-12
+
+
 def test_gridding_is_adjoint_nudft():
     g, traj, rng, _ = tiny_geometry()
     y = crand(rng, 2, traj.size // 2)
