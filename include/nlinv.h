@@ -16,7 +16,8 @@
  *    grid oversampling; 2N unless given), R = G/2 reconstructed side,
  *    G_c = G/4 coil-spectrum side (Sec. 3.2, coil cropping),
  *    S = K * S_r samples per channel, X = R*R + J*G_c*G_c unknowns.
- *    Supported grids: G in {64, 128, 256, 320, 384, 448} with 2N <= G <= 4N.
+ *    Supported grids: G in {64, 128, 256, 320, 384, 448, 480, 512} with
+ *    2N <= G <= 4N.
  *    Every array is on the R x R field of view; for gamma > 1 the N x N
  *    output image is its centre, rows and columns R/2 - floor(N/2) to
  *    R/2 + ceil(N/2) - 1.

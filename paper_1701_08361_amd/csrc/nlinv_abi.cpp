@@ -64,7 +64,7 @@ int fail_hip(nlinv_plan plan, hipError_t e, const char* what) {
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 bool supported_grid(int G) {
-  return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 448;
+  return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 448 || G == 480 || G == 512;
 }
 
 // Kaiser-Bessel gridding kernel (Beatty, Nishimura, Pauly 2005): width W grid
@@ -156,7 +156,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   // view R = G/2 holds the N x N image in its centre
   const int G = p->G == 0 ? 2 * p->N : p->G;
   if (G < 2 * p->N || G > 4 * p->N) return bad(NLINV_E_SIZE, "G must be in [2N, 4N] (G = 2 gamma N, 1 <= gamma <= 2)");
-  if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384 or 448");
+  if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384, 448, 480 or 512");
   if (p->J < 1 || p->J > 64) return bad(NLINV_E_ARG, "J must be in [1, 64]");
   if (p->K < 1 || (p->K % 2) == 0) return bad(NLINV_E_ARG, "K must be a positive odd number");
   const int S_r = p->S_r == 0 ? 2 * p->N : p->S_r;

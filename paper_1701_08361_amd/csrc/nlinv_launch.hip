@@ -12,6 +12,8 @@ const GTable* table_g256();
 const GTable* table_g320();
 const GTable* table_g384();
 const GTable* table_g448();
+const GTable* table_g480();
+const GTable* table_g512();
 
 const GTable* table_for(int G) {
   switch (G) {
@@ -21,6 +23,8 @@ const GTable* table_for(int G) {
     case 320: return table_g320();
     case 384: return table_g384();
     case 448: return table_g448();
+    case 480: return table_g480();
+    case 512: return table_g512();
     default: return nullptr;
   }
 }
@@ -215,7 +219,8 @@ __device__ __forceinline__ float2 cis_cycles(float k, int m) {
 constexpr int GSC = 64;   // samples per LDS stage
 constexpr int GT = 16;    // pixel tile side (16 x 16 = 256 threads)
 
-// Gridding, register-blocked: a block owns a 32 x 32 pixel tile and JG channels,
+// Gridding, register-blocked: a block owns a 32 x 32 pixel tile and JG channels
+// (the last tile row and column are partial when R is not a multiple of 32),
 // each thread a 2 x 2 pixel patch; samples are staged in LDS 32 at a time
 // (phase factors exp(+i 2 pi k x) and exp(+i 2 pi k y) per sample and tile row /
 // column), float32 sums per stage are accumulated in float64.  With nsplit > 1
@@ -229,7 +234,7 @@ k_grid2(const float* __restrict__ traj, const float2* __restrict__ yv, float2* _
   __shared__ __align__(16) float2 ex[GS2][32];
   __shared__ __align__(16) float2 ey[GS2][32];
   __shared__ float2 ys[JG][GS2];
-  const int nt = R / 32;
+  const int nt = (R + 31) / 32;
   const int ty0 = (blockIdx.x / nt) * 32, tx0 = (blockIdx.x % nt) * 32;
   const int jg = blockIdx.y;
   const int b = blockIdx.z / nsplit, sp = blockIdx.z - b * nsplit;
@@ -301,8 +306,9 @@ k_grid2(const float* __restrict__ traj, const float2* __restrict__ yv, float2* _
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int y = ty0 + 2 * ty + (k >> 1), x = tx0 + 2 * tx + (k & 1);
-      o[(((size_t)b * J + j) * R + y) * R + x] =
-          make_float2((float)(acc[q][k].x * scale), (float)(acc[q][k].y * scale));
+      if (y < R && x < R)
+        o[(((size_t)b * J + j) * R + y) * R + x] =
+            make_float2((float)(acc[q][k].x * scale), (float)(acc[q][k].y * scale));
     }
   }
 }
@@ -355,11 +361,12 @@ k_psf_lags(const float* __restrict__ traj, double2* __restrict__ psf, int S, int
 }
 
 // y[b][j][s] = scale sum_{y,x} u[b][j][y][x] exp(-i 2 pi (kx_s x + ky_s y))
-constexpr int FXC = 32;   // x chunk
+constexpr int FXC = 32;           // x chunk
+constexpr int NUDFT_MAXR = 256;   // largest field of view (64 KB of LDS per block)
 __global__ void __launch_bounds__(VT)
 k_nudft_fwd(const float* __restrict__ traj, const float2* __restrict__ u, float2* __restrict__ yv,
             int J, int S, int R, float scale) {
-  __shared__ float2 uc[224 * FXC];
+  __shared__ float2 uc[NUDFT_MAXR * FXC];
   const int s = blockIdx.x * VT + threadIdx.x;
   const int j = blockIdx.y, b = blockIdx.z;
   const bool valid = s < S;
@@ -370,8 +377,8 @@ k_nudft_fwd(const float* __restrict__ traj, const float2* __restrict__ u, float2
   for (int x0 = 0; x0 < R; x0 += FXC) {
     __syncthreads();
     for (int q = threadIdx.x; q < R * FXC; q += VT) {
-      const int yy = q / FXC, xx = q % FXC;
-      uc[q] = ub[(size_t)yy * R + x0 + xx];
+      const int yy = q / FXC, xx = q % FXC;   // columns past R (last chunk) are zero
+      uc[q] = x0 + xx < R ? ub[(size_t)yy * R + x0 + xx] : czero<float2>();
     }
     __syncthreads();
     float2 exv[FXC];
@@ -514,7 +521,8 @@ int grid_jg(int J) {
 }
 
 int grid_nsplit(int B, int J, int R) {
-  const long long blocks = (long long)(R / 32) * (R / 32) * ((J + grid_jg(J) - 1) / grid_jg(J)) * B;
+  const long long nt = (R + 31) / 32;
+  const long long blocks = nt * nt * ((J + grid_jg(J) - 1) / grid_jg(J)) * B;
   int n = 1;
   while (n < 8 && blocks * n < 512) n *= 2;
   return n;
@@ -525,7 +533,8 @@ hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const floa
   const int JG = grid_jg(s.J);
   const int nsplit = s.gsplit;
   float2* out = nsplit > 1 ? w.GS : z;
-  dim3 grid((s.R / 32) * (s.R / 32), (s.J + JG - 1) / JG, s.B * nsplit);
+  const int nt = (s.R + 31) / 32;
+  dim3 grid(nt * nt, (s.J + JG - 1) / JG, s.B * nsplit);
   const float scale = 1.0f / s.R;
   switch (JG) {
     case 5: k_grid2<5><<<grid, VT, 0, st>>>(traj, y, out, s.J, s.S, s.R, s.B, nsplit, scale); break;
@@ -543,7 +552,7 @@ hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const floa
 
 hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
                             float2* y) {
-  if (s.R > 224 || s.R % FXC) return hipErrorInvalidValue;
+  if (s.R > NUDFT_MAXR) return hipErrorInvalidValue;
   dim3 grid((s.S + VT - 1) / VT, s.J, s.B);
   k_nudft_fwd<<<grid, VT, 0, st>>>(traj, u, y, s.J, s.S, s.R, 1.0f / s.R);
   return hipGetLastError();

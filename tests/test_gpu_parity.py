@@ -74,7 +74,8 @@ def test_grid_ragged_readout(torch):
         assert rel(z[0], ref) < 1e-6
 
 
-@pytest.mark.parametrize("N,J,K,seed", [(32, 3, 5, 11), (64, 8, 13, 1), (160, 10, 15, 2)])
+@pytest.mark.parametrize("N,J,K,seed", [(32, 3, 5, 11), (64, 8, 13, 1), (160, 10, 15, 2),
+                                        (240, 3, 5, 4)])   # partial 32 x 32 pixel tiles
 def test_grid_matches_exact_adjoint_nudft(torch, N, J, K, seed):
     """Kaiser-Bessel gridding (turns given, the default) and the exact sum
     (NLINV_F_EXACT_GRID, and calls without turns) against the oracle's exact sum."""
@@ -91,7 +92,7 @@ def test_grid_matches_exact_adjoint_nudft(torch, N, J, K, seed):
         assert rel(z[0], ref) < 1e-6
 
 
-@pytest.mark.parametrize("N,J", [(32, 2), (64, 8), (128, 5), (160, 10), (192, 3), (224, 4)])
+@pytest.mark.parametrize("N,J", [(32, 2), (64, 8), (128, 5), (160, 10), (192, 3), (224, 4), (240, 3), (256, 2)])
 def test_coil_synthesis(torch, N, J):
     print_case("coils", N=N, J=J)
     plan = nl().Plan(N, J, 5)
@@ -130,7 +131,7 @@ def _normal_case(torch, N, J, K, U, B, alpha, seed):
 @pytest.mark.parametrize("N,J,K,U,B,alpha", [
     (32, 2, 5, 1, 1, 0.0), (64, 8, 13, 2, 3, 0.37), (64, 8, 13, 1, 1, 0.0),
     (128, 4, 11, 3, 2, 0.0), (160, 10, 15, 5, 2, 0.125), (192, 3, 9, 1, 1, 0.0),
-    (224, 5, 21, 2, 2, 0.5),
+    (224, 5, 21, 2, 2, 0.5), (240, 3, 9, 1, 1, 0.25), (256, 2, 11, 2, 2, 0.0),
     (32, 64, 5, 2, 2, 0.1),     # the most channels a plan takes
     (32, 2, 3, 4, 64, 0.0)])    # the largest batch
 def test_normal_operator(torch, N, J, K, U, B, alpha):
@@ -142,7 +143,8 @@ def test_normal_operator(torch, N, J, K, U, B, alpha):
 # operators on radial samples
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("N,J,K,B", [(32, 2, 5, 1), (64, 8, 13, 2), (160, 10, 15, 1)])
+@pytest.mark.parametrize("N,J,K,B", [(32, 2, 5, 1), (64, 8, 13, 2), (160, 10, 15, 1),
+                                     (240, 2, 5, 1)])   # field of view not a multiple of the x chunk
 def test_F_DF_DFH_match_oracle(torch, N, J, K, B):
     print_case("F/DF/DFH", N=N, J=J, K=K, B=B)
     plan = nl().Plan(N, J, K, batch=B)
@@ -206,7 +208,8 @@ def test_reconstruct_single_frame_c1(torch):
 @pytest.mark.parametrize("N,J,K,M,C", [
     (128, 8, 11, 4, 8),     # smallest mixed-size configuration (256 grid)
     (192, 16, 21, 3, 6),    # largest mixed-size configuration (384 grid, 16 coils, 21 spokes)
-    (224, 16, 21, 2, 4),    # largest supported grid (448), 16 coils
+    (224, 16, 21, 2, 4),    # 448 grid, 16 coils
+    (256, 4, 9, 2, 3),      # largest supported grid (512)
     (32, 1, 1, 3, 4),       # degenerate: one coil, one spoke
     (32, 64, 5, 2, 3),      # the most channels a plan takes
 ])

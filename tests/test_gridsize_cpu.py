@@ -32,13 +32,14 @@ def _printed_rows():
 
 
 def test_supported_grids_come_from_the_library(lib):
-    assert GS.supported_grids(nl) == [64, 128, 256, 320, 384, 448]
+    assert GS.supported_grids(nl) == [64, 128, 256, 320, 384, 448, 480, 512]
 
 
 @pytest.mark.parametrize("N,G,expect", [
     (160, 448, dict(R=224, G=448, Gc=112, S=15 * 320, X=224 * 224 + 10 * 112 * 112)),   # gamma 1.4
     (128, 384, dict(R=192, G=384, Gc=96, S=15 * 256, X=192 * 192 + 10 * 96 * 96)),      # gamma 1.5
     (32, 128, dict(R=64, G=128, Gc=32, S=15 * 64, X=64 * 64 + 10 * 32 * 32)),           # gamma 2
+    (170, 512, dict(R=256, G=512, Gc=128, S=15 * 340, X=256 * 256 + 10 * 128 * 128)),  # Table oversampling_ratio
 ])
 def test_abi_takes_gamma_above_one(lib, N, G, expect):
     """R = G/2 widens the field of view; the readout keeps 2N samples."""
