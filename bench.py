@@ -77,6 +77,8 @@ def measured_traffic(kind: str):
     return out
 
 
+COL_TILE = 0   # tile schedule of the plain, relaxed and batched plans (--col-tile)
+
 # Mixed sizes: (N, J, K, series) per shape, 16 series in all
 MIXED = [(128, 8, 11, 5), (160, 10, 15, 6), (192, 16, 21, 5)]
 # Streaming slices: (N, J virtual, J_phys receive channels, K)
@@ -131,7 +133,7 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, g
     with HIP events around every launch of `timer_kernel`.  Returns per-step ms,
     total ms of the timed steps, and the kernel timer reading (ms, launches).
     img_store[n] (optional) receives the image of frame n of item 0."""
-    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=(1 if fast else 0))
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=(1 if fast else 0), col_tile=COL_TILE)
     plan.set_graphs(graphs)
     import numpy as np
     traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()  # [F,B,K,S_r,2]
@@ -192,7 +194,7 @@ def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None):
     order, then groups of o frames (nlinv_reconstruct_frames).  Times the
     groups that start at or after frame `warmup`, about `steps` frames.
     Returns (frames timed, total ms, per-group ms, frames processed)."""
-    plan = nl.Plan(N, J, K, U=U, batch=o, newton=M, cg=C)
+    plan = nl.Plan(N, J, K, U=U, batch=o, newton=M, cg=C, col_tile=COL_TILE)
     plan.set_graphs(graphs)
     traj = torch.from_numpy(data[0][0]).cuda()      # [F, K, S_r, 2]
     y = torch.from_numpy(data[0][1]).cuda()         # [F, J, S]
@@ -404,7 +406,8 @@ def run_diff(torch, nl, data, steps, newton, cg):
 def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
     """The autotuner's learning mode on the 160 px series for several series
     lengths: every setting (T frames per relaxed group = 1..8, A = 1, HIP
-    graphs off / on) reconstructs the first `frames` frames, the database
+    graphs off / on, column-pass tiles of 8 or 4 columns) reconstructs the
+    first `frames` frames, the database
     records each rate, and the worst and best settings are reported per
     length.  Rates include gridding and graph captures; plans and PSF kernels
     are built before the clock starts."""
@@ -417,7 +420,7 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
     for frames in frame_counts:
         frames = min(frames, traj_all.shape[0])
         p = dict(mode="single-slice", N=N, J=J, K=K, U=U, frames=frames, newton=M, cg=C)
-        tuner = AT.Autotuner(db, learning=True)
+        tuner = AT.Autotuner(db, learning=True, tiles=(8, 4))
         if not graphs_allowed:
             tuner.space = [c for c in tuner.space if not c["graphs"]]
         tuner.learn(p, lambda c: AT.run_series(nl, torch, traj_all[:frames], y_all[:frames],
@@ -425,11 +428,12 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
         hits = db.lookup(p)
         (bc, bf), (wc, wf) = hits[0], hits[-1]
         rows.append({"frames": frames, "settings": len(hits),
-                     "worst": {"T": wc["T"], "A": wc["A"], "graphs": wc["graphs"], "fps": wf},
-                     "best": {"T": bc["T"], "A": bc["A"], "graphs": bc["graphs"], "fps": bf},
-                     "all": [[c["T"], c["graphs"], round(f, 1)] for c, f in hits]})
+                     "worst": dict(wc, fps=wf), "best": dict(bc, fps=bf),
+                     "all": [[c["T"], c["graphs"], c["col_tile"], round(f, 1)] for c, f in hits]})
     return {"form": "learning mode over T = 1..8 frames per relaxed group (l = 5 strict frames first), A = 1, "
-                    "HIP graphs off/on; rate = frames / wall time of the whole series (gridding + reconstruction)",
+                    "HIP graphs off/on, column-pass tile schedule 8 or 4 columns per block; rate = frames / "
+                    "wall time of the whole series (gridding + reconstruction); 'all' rows are "
+                    "[T, graphs, col_tile, fps]",
             "by_frames": rows}
 
 
@@ -573,9 +577,13 @@ def main():
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
     ap.add_argument("--autotune-frames", default="5,10,25,50",
                     help="series lengths of the autotuning run (learning mode over all settings; '' = skip)")
+    ap.add_argument("--col-tile", type=int, default=0, choices=[0, 4, 8],
+                    help="columns per block of the CG column passes (0 = the library's choice)")
     ap.add_argument("--grid-lut-reps", type=int, default=30,
                     help="applications timed per grid side for the grid-size lookup table (0 = skip)")
     args = ap.parse_args()
+    global COL_TILE
+    COL_TILE = args.col_tile
     if args.source_hash:
         print(kernel_source_hash())
         return

@@ -102,6 +102,9 @@ typedef struct {
   double alpha_min;   /* (default 0.0)                                           */
   double sob_a;       /* Sobolev weight (1 + a |k|^2)^l, Fig. weight_func: 880   */
   double sob_l;       /*                                                    : 16 */
+  int32_t col_tile;   /* tile schedule: columns per block of the two column    */
+                      /* passes of a CG iteration, 0 or 8 (default) or 4       */
+                      /* (twice the blocks); results are identical bit for bit */
 } nlinv_params;
 
 /* Fill `p` with the defaults above (N, K left 0).  Never fails for non-NULL p. */

@@ -21,6 +21,9 @@ decomposition).  On one GPU the setting is
          of every later frame, so the better choice depends on the number of
          frames.
 The search space for A = 1 is T = 1..8, as in the paper, times graphs off/on.
+A tuner may also search the tile schedule of the CG column passes
+(col_tile: columns per block, 8 or 4; the same images bit for bit), so that
+the kernel decomposition is measured per protocol instead of fixed.
 
 The database is a JSON file (a list of records); the runner reconstructs a
 whole series through the C-ABI and measures it with the host clock around
@@ -33,7 +36,7 @@ import math
 import os
 import tempfile
 import time
-from typing import Callable, Dict, List, Optional, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 PROTOCOL_KEYS = ("mode", "N", "J", "K", "U", "frames", "newton", "cg")
 
@@ -45,10 +48,13 @@ def _norm_protocol(p: Dict) -> Dict:
     return {k: p[k] for k in PROTOCOL_KEYS}
 
 
-def search_space(gpus: int = 1, max_T: int = 8) -> List[Dict]:
+def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] = None) -> List[Dict]:
     """Settings (T, A, graphs): for A = 1, T = 1..max_T; for A = 2 up to
     max_T / 2; for A = 3, 4 up to max_T / 4 (the paper's limits on 8 GPUs),
-    with A <= gpus; each with graphs off and on."""
+    with A <= gpus; each with graphs off and on; with `tiles`, each also with
+    every listed column-pass tile schedule (col_tile)."""
+    if tiles is not None and (not tiles or any(t not in (4, 8) for t in tiles)):
+        raise ValueError("tile schedules are 4 or 8 columns per block")
     out = []
     for A in (1, 2, 3, 4):
         if A > gpus:
@@ -56,7 +62,10 @@ def search_space(gpus: int = 1, max_T: int = 8) -> List[Dict]:
         tmax = max_T if A == 1 else (max_T // 2 if A == 2 else max(1, max_T // 4))
         for T in range(1, tmax + 1):
             for graphs in (False, True):
-                out.append({"T": T, "A": A, "graphs": graphs})
+                if tiles is None:
+                    out.append({"T": T, "A": A, "graphs": graphs})
+                else:
+                    out.extend({"T": T, "A": A, "graphs": graphs, "col_tile": int(t)} for t in tiles)
     return out
 
 
@@ -115,9 +124,10 @@ def protocol_distance(a: Dict, b: Dict) -> float:
 
 
 class Autotuner:
-    def __init__(self, db: TuningDB, gpus: int = 1, max_T: int = 8, learning: bool = False):
+    def __init__(self, db: TuningDB, gpus: int = 1, max_T: int = 8, learning: bool = False,
+                 tiles: Optional[Sequence[int]] = None):
         self.db, self.learning = db, learning
-        self.space = search_space(gpus, max_T)
+        self.space = search_space(gpus, max_T, tiles)
 
     def untried(self, protocol: Dict) -> List[Dict]:
         tried = [c for c, _ in self.db.lookup(protocol)]
@@ -169,7 +179,7 @@ def run_series(nl, torch, traj, y, turns, config: Dict, newton: int, cg: int, U:
     N = int(round(traj.shape[2] / 2))
     K = traj.shape[1]
     l = U if l is None else l
-    plan = nl.Plan(N, J, K, U=U, batch=T, newton=newton, cg=cg)
+    plan = nl.Plan(N, J, K, U=U, batch=T, newton=newton, cg=cg, col_tile=int(config.get("col_tile", 0)))
     try:
         plan.set_graphs(bool(config.get("graphs", True)))
         for t in range(min(U, F)):

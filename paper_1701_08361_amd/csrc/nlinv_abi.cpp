@@ -172,6 +172,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (!(p->alpha_min >= 0.0) || !std::isfinite(p->alpha_min)) return bad(NLINV_E_ARG, "alpha_min must be >= 0");
   if (!(p->sob_a >= 0.0) || !(p->sob_l >= 0.0) || !std::isfinite(p->sob_a) || !std::isfinite(p->sob_l))
     return bad(NLINV_E_ARG, "Sobolev parameters must be finite and >= 0");
+  if (p->col_tile != 0 && p->col_tile != 4 && p->col_tile != 8) return bad(NLINV_E_ARG, "col_tile must be 0, 4 or 8");
 
   Shape& S = *s;
   S.B = p->batch;
@@ -194,6 +195,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (S.NCH > st) st = S.NCH;
   S.stride = st;
   S.fast = (p->flags & NLINV_F_FAST) != 0;
+  S.coltile = p->col_tile;
   S.gsplit = nlv::grid_nsplit(S.B, S.J, S.R);
   // Kaiser-Bessel gridding tables: (W + 1)^2 entries per sample and turn; left
   // out (exact gridding only) when they would take more than 2 GiB

@@ -40,7 +40,17 @@ struct Shape {
   int gsplit;          // sample-range split of the gridding kernel (1 = none)
   bool kb;             // Kaiser-Bessel gridding tables present
   long long kbe_stride;  // table entries per turn
+  int coltile;         // tile schedule of cols_fwd / cols_back: 0 (the library's), 4 or 8
 };
+
+// Columns per block of a CG column pass (the plan's tile schedule; the
+// library's choice is TW for both passes).  Four columns per block double
+// the blocks of launches too small to fill the GPU; measured at 160 px they
+// speed up the forward pass of a batch-1 launch alone, yet the whole solve
+// runs slower (plain series 164.8 against 166.9 frames/s with four columns in
+// the forward pass of small launches only), so four is a schedule to measure,
+// not a default.
+inline int col_tile(const Shape& s, bool /*forward*/) { return s.coltile == 4 ? 4 : TW; }
 
 // Gridding work decomposition (channels per block; sample-range split).
 int grid_jg(int J);

@@ -45,7 +45,7 @@ template <int G> constexpr int rows_threads() { return pad64(ROWS * Team<G>::SIZ
 // share a CU (measured: Toeplitz pass 15 % faster than 8-line blocks).
 template <int G> constexpr int row_lines() { return 64 / Team<G>::SIZE > 0 ? 64 / Team<G>::SIZE : 1; }
 template <int G> constexpr int row_threads() { return pad64(row_lines<G>() * Team<G>::SIZE); }
-template <int G> constexpr int cols_threads() { return pad64(TW * Team<G>::SIZE); }
+template <int G, int TWC = TW> constexpr int cols_threads() { return pad64(TWC * Team<G>::SIZE); }
 
 // ---------------------------------------------------------------------------
 // reductions (FP64, fixed order, valid for blocks that are not whole waves)
@@ -269,20 +269,20 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
 // MODE 1: u = c_j d_rho + rho d_c_j -> out (U2);  MODE 2 / 3: as 0 / 1 but u -> out (image, float32)
 // pv: the direction (MODE 1 / 3), its rho block already updated by coil_rows.
 // ---------------------------------------------------------------------------
-template <int G, int MODE, class S2>
-__global__ void __launch_bounds__(cols_threads<G>())
+template <int G, int TWC, int MODE, class S2>
+__global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2* __restrict__ xh,
            const double2* __restrict__ pv, const double2* __restrict__ tw, void* __restrict__ outp, int J,
            long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TWC;
   constexpr bool NORMAL = (MODE == 1 || MODE == 3);
   constexpr bool TO_IMG = (MODE == 2 || MODE == 3);
-  __shared__ C lds[TW * T::LDSC];
-  const bool act = (int)threadIdx.x < TW * T::SIZE;
-  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
+  __shared__ C lds[TWC * T::LDSC];
+  const bool act = (int)threadIdx.x < TWC * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
-  const int x = tile * TW + col;
+  const int x = tile * TWC + col;
   C* L = lds + col * T::LDSC;
 
   // the coil-row, rho and coil-image loads are issued before the first exchange,
@@ -403,18 +403,18 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
 // to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32),
 // 3 plain W^-H column stage of coil images `in` (no channel products, no rho).
 // ---------------------------------------------------------------------------
-template <int G, int MODE, class S2>
-__global__ void __launch_bounds__(cols_threads<G>())
+template <int G, int TWC, int MODE, class S2>
+__global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
             const float2* __restrict__ z, const double2* __restrict__ tw, float2* __restrict__ PR,
             double2* __restrict__ U4, int J, long long X) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TW;
-  __shared__ C lds[TW * T::LDSC];
-  const bool act = (int)threadIdx.x < TW * T::SIZE;
-  const int col = act ? (int)threadIdx.x % TW : 0, tl = act ? (int)threadIdx.x / TW : T::SIZE;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TWC;
+  __shared__ C lds[TWC * T::LDSC];
+  const bool act = (int)threadIdx.x < TWC * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
-  const int x = tile * TW + col;
+  const int x = tile * TWC + col;
   C* L = lds + col * T::LDSC;
   const size_t img = (size_t)bj * R * R;
 
@@ -796,22 +796,28 @@ struct GLaunch {
                         pdst, sc, (const float*)w.dinv, (const double2*)w.tw, w.U1, s.J, (long long)s.X,
                         s.NX3, nr);
   }
-  template <class S2>
-  static hipError_t cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
+  template <class S2, int TWC>
+  static hipError_t cols_fwd_k(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
                                const float2* xh, const double2* pv, void* out) {
-    const int blocks = s.B * s.J * s.NT;
+    constexpr int TH = cols_threads<G, TWC>();
+    const int blocks = s.B * s.J * (s.R / TWC);
     switch (mode) {
-      case 0: return launch_timed(w, k_cols_fwd<G, 0, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+      case 0: return launch_timed(w, k_cols_fwd<G, TWC, 0, S2>, dim3(blocks), dim3(TH), 0, st,
                                    (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
-      case 1: return launch_timed(w, k_cols_fwd<G, 1, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+      case 1: return launch_timed(w, k_cols_fwd<G, TWC, 1, S2>, dim3(blocks), dim3(TH), 0, st,
                                    (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
-      case 2: return launch_timed(w, k_cols_fwd<G, 2, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+      case 2: return launch_timed(w, k_cols_fwd<G, TWC, 2, S2>, dim3(blocks), dim3(TH), 0, st,
                                    (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
-      case 3: return launch_timed(w, k_cols_fwd<G, 3, S2>, dim3(blocks), dim3(TH_COLS), 0, st,
+      case 3: return launch_timed(w, k_cols_fwd<G, TWC, 3, S2>, dim3(blocks), dim3(TH), 0, st,
                                    (const double2*)w.U1, co, xh, pv, (const double2*)w.tw, out, s.J, (long long)s.X);
       default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+  }
+  template <class S2>
+  static hipError_t cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
+                               const float2* xh, const double2* pv, void* out) {
+    return col_tile(s, true) == 4 ? cols_fwd_k<S2, 4>(s, w, st, mode, co, xh, pv, out)
+                                  : cols_fwd_k<S2, TW>(s, w, st, mode, co, xh, pv, out);
   }
   static hipError_t cols_fwd(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
                              const float2* xh, const double2* pv, void* out) {
@@ -829,22 +835,28 @@ struct GLaunch {
   static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
     return s.fast ? toep_rows_t<float2>(s, w, st, turns) : toep_rows_t<double2>(s, w, st, turns);
   }
-  template <class S2>
-  static hipError_t cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
+  template <class S2, int TWC>
+  static hipError_t cols_back_k(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
                                 const float2* co, const float2* xh, const float2* z) {
-    const int blocks = s.B * s.J * s.NT;
+    constexpr int TH = cols_threads<G, TWC>();
+    const int blocks = s.B * s.J * (s.R / TWC);
     switch (mode) {
-      case 0: return launch_timed(w, k_cols_back<G, 0, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+      case 0: return launch_timed(w, k_cols_back<G, TWC, 0, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
                                    (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
-      case 1: return launch_timed(w, k_cols_back<G, 1, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+      case 1: return launch_timed(w, k_cols_back<G, TWC, 1, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
                                    (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
-      case 2: return launch_timed(w, k_cols_back<G, 2, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+      case 2: return launch_timed(w, k_cols_back<G, TWC, 2, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
                                    (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
-      case 3: return launch_timed(w, k_cols_back<G, 3, S2>, dim3(blocks), dim3(TH_COLS), 0, st, in, co, xh, z,
+      case 3: return launch_timed(w, k_cols_back<G, TWC, 3, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
                                    (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
       default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+  }
+  template <class S2>
+  static hipError_t cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
+                                const float2* co, const float2* xh, const float2* z) {
+    return col_tile(s, false) == 4 ? cols_back_k<S2, 4>(s, w, st, mode, in, co, xh, z)
+                                  : cols_back_k<S2, TW>(s, w, st, mode, in, co, xh, z);
   }
   static hipError_t cols_back(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
                               const float2* co, const float2* xh, const float2* z) {

@@ -29,6 +29,20 @@ def test_search_space_matches_the_papers_limits():
     assert eight == paper and len(paper) == 16
 
 
+def test_tile_schedule_dimension():
+    """With tiles, every (T, A, graphs) setting comes with each column-pass
+    tile schedule; the learning mode then measures the schedules too."""
+    sp = AT.search_space(1, tiles=(8, 4))
+    assert len(sp) == 32 and {c["col_tile"] for c in sp} == {4, 8}
+    assert {(c["T"], c["graphs"]) for c in sp} == {(c["T"], c["graphs"]) for c in AT.search_space(1)}
+    with pytest.raises(ValueError):
+        AT.search_space(1, tiles=(16,))
+    rate = lambda c: fake_rate(c) + (0.5 if c["col_tile"] == 4 else 0.0)
+    tuner = AT.Autotuner(AT.TuningDB(), learning=True, tiles=(8, 4))
+    best = tuner.learn(proto(), rate)
+    assert best == {"T": 3, "A": 1, "graphs": True, "col_tile": 4}
+
+
 def test_learning_mode_tries_every_setting_then_the_best_wins(tmp_path):
     db = AT.TuningDB(str(tmp_path / "tune.json"))
     tuner = AT.Autotuner(db, learning=True)

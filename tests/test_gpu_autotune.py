@@ -34,6 +34,9 @@ def test_runner_settings_and_learning(torch, tmp_path):
         fb, ib = run({"T": T, "A": 1, "graphs": True})
         assert fa > 0 and fb > 0
         assert torch.equal(ia, ib), T
+    # the column-pass tile schedule changes the decomposition, never the result
+    _, i4 = run({"T": 3, "A": 1, "graphs": True, "col_tile": 4})
+    assert torch.equal(i4, ib)
     # the strict setting reproduces plain frame-by-frame reconstruction
     plan = nlinv.Plan(N, J, K, U=U, newton=M, cg=C)
     for t in range(U):

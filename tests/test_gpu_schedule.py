@@ -1,0 +1,60 @@
+"""Tile schedules of the CG column passes (columns per block, 8 or 4): the
+decomposition changes which block computes a column, not the arithmetic of
+any column, so reconstructions and operator applications agree bit for bit,
+and with the oracle to the usual bars."""
+import numpy as np
+import pytest
+
+from oracle import nlinv_oracle as O
+from paper_1701_08361_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1701_08361_amd import nlinv
+    nlinv.load()
+    return _t
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("N,J,K,B,G", [(64, 8, 13, 3, 0), (160, 10, 15, 1, 0), (120, 3, 9, 2, 480)])
+def test_column_tiles_agree_bit_for_bit(torch, N, J, K, B, G):
+    from paper_1701_08361_amd import nlinv as nl
+    print(f"[case] column tiles N={N} J={J} K={K} B={B} G={G}", flush=True)
+    s = [synth.single_frame(seed=20 + b, N=N, J=J, K=K) for b in range(B)]
+    traj = torch.from_numpy(np.concatenate([f.traj for f in s])).cuda()
+    y = torch.from_numpy(np.concatenate([f.y for f in s])).cuda()
+    out = {}
+    for tile in (0, 4, 8):
+        plan = nl.Plan(N, J, K, batch=B, newton=3, cg=6, G=G, col_tile=tile)
+        z = plan.grid(traj, y, turns=[0] * B) if B == 1 else None
+        if B > 1:
+            plan.psf(traj[0].contiguous(), 0)
+            z = plan.grid(traj, y)
+        x, img, _ = plan.reconstruct(z, [0] * B, want_img=True)
+        p = torch.from_numpy(np.stack([synth.random_xhat(5 + b, plan.R, J, plan.Gc) for b in range(B)])).cuda()
+        q = plan.apply_normal([0] * B, x, p, 0.25)
+        torch.cuda.synchronize()
+        out[tile] = (x.cpu().numpy(), img.cpu().numpy(), q.cpu().numpy(), plan)
+    for tile in (4, 8):
+        for a, b in zip(out[0][:3], out[tile][:3]):
+            assert np.array_equal(a, b), f"col_tile={tile} differs from the default"
+    # and the default against the oracle (first item)
+    plan = out[0][3]
+    g = O.Geometry.make(N, J, plan.G)
+    P = O.psf_kernel(s[0].traj[0], g.R, g.G)
+    xr = O.reconstruct(g, O.grid(s[0].y[0], s[0].traj[0], g.R), P, newton=3, cg_iters=6)
+    e = rel(out[0][1][0], O.image(g, xr))
+    print(f"image rel {e:.2e}")
+    assert e < 1e-3
+    for t in out.values():
+        t[3].close()
