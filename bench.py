@@ -452,8 +452,45 @@ def run_grid_choice(torch, nl, reps):
             choice[str(n)] = {"G": g, "gamma": round(GS.gamma(n, g), 5)}
         except ValueError:
             choice[str(n)] = None
+    # Table oversampling_ratio on this GPU where both grids are supported:
+    # frames/s of the plain solve (7 x 20, each frame regularised to the
+    # previous result) at the fixed gamma = 1.5 grid and at the chosen one
+    from paper_1701_08361_amd import synth
+    table = []
+    for n in (128, 160, 170):
+        g_fix = 3 * n
+        row = {"N": n, "G_fixed": g_fix, "fps_fixed": None}
+        if g_fix in grids:
+            row["fps_fixed"] = round(_grid_fps(torch, nl, synth, n, g_fix), 1)
+        g_opt = choice[str(n)]["G"] if choice[str(n)] else None
+        row.update({"G_chosen": g_opt, "fps_chosen": round(_grid_fps(torch, nl, synth, n, g_opt), 1) if g_opt else None})
+        if row["fps_fixed"] and row["fps_chosen"]:
+            row["speedup"] = round(row["fps_chosen"] / row["fps_fixed"], 3)
+        table.append(row)
     return {"us_per_normal_application": {str(g): round(t, 2) for g, t in lut.items()},
-            "J": J, "K": K, "reps": reps, "choice_gamma_min_1_4": choice}
+            "J": J, "K": K, "reps": reps, "choice_gamma_min_1_4": choice, "oversampling_table": table}
+
+
+def _grid_fps(torch, nl, synth, n, G, frames=20):
+    """Frames/s of the plain 7 x 20 solve of one synthetic 10-coil, 15-spoke
+    frame on grid G, each frame regularised to the previous result."""
+    s = synth.single_frame(seed=3, N=n, J=J, K=K)
+    plan = nl.Plan(n, J, K, G=G, newton=M, cg=C)
+    try:
+        z = plan.grid(torch.from_numpy(s.traj).cuda(), torch.from_numpy(s.y).cuda(), turns=[0])
+        xb = [plan.empty(1, plan.X) for _ in range(2)]
+        img = torch.empty(1, plan.R, plan.R, dtype=torch.float32, device=plan.device)
+        prev = None
+        for f in range(frames + 3):
+            if f == 3:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            plan.reconstruct(z, [0], xprev=prev, xhat=xb[f % 2], init=1 if prev is None else 2, img=img)
+            prev = xb[f % 2]
+        torch.cuda.synchronize()
+        return frames / (time.perf_counter() - t0)
+    finally:
+        plan.close()
 
 
 def run_pipeline(torch, raw, periods, period_ms, shared, graphs):
