@@ -66,3 +66,17 @@ def test_measured_table_and_choice(torch):
     assert GS.choose(64, lut, gamma_min=1.0) == 128       # the only grid with 1 <= gamma <= 2
     with pytest.raises(ValueError):
         GS.choose(64, lut)                                  # gamma >= 1.4 needs 179.2 <= G <= 256
+
+
+def test_lookup_table_is_measured_once_per_device(torch, tmp_path, monkeypatch):
+    from paper_1701_08361_amd import gridsize as GS
+    from paper_1701_08361_amd import nlinv as nl
+    print("[case] grid lookup table file 128/256", flush=True)
+    path = str(tmp_path / "grids.json")
+    lut = GS.GridLUT(path).table(nl, torch, J=2, K=5, grids=[128, 256], reps=3)
+    assert sorted(lut) == [128, 256] and all(t > 0 for t in lut.values())
+    # a second process finds the stored table and measures nothing
+    monkeypatch.setattr(GS, "measure", lambda *a, **k: pytest.fail("measured again"))
+    assert GS.GridLUT(path).table(nl, torch, J=2, K=5, grids=[128, 256]) == lut
+    key = GS.GridLUT.key(torch.cuda.get_device_name(), GS.library_digest(nl), 2)
+    assert GS.GridLUT(path).get(key) == lut
