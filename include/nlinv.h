@@ -147,6 +147,16 @@ int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn);
  * nlinv_psf(plan, d_traj, turn) is nlinv_psf_spokes(plan, d_traj, K, turn). */
 int nlinv_psf_spokes(nlinv_plan plan, const float* d_traj, int32_t spokes, int32_t turn);
 
+/* The same for a turn of any smaller acquisition: only the first `samples`
+ * samples of d_traj (1 <= samples <= K * S_r, NLINV_E_ARG otherwise) count,
+ * so a series with fewer samples per spoke (a smaller image side N' on this
+ * plan's grid, gamma = G / (2 N') <= 2, Sec. 3.2) or fewer spokes packs its
+ * K' * S_r' samples at the start of the plan's [J][K * S_r] layout and runs
+ * in the same batched launch; with zero channels for a smaller coil count its
+ * reconstruction equals that of its own plan of grid G bit for bit.  The
+ * same zero-sample rule as nlinv_psf_spokes holds for the exact sum. */
+int nlinv_psf_samples(nlinv_plan plan, const float* d_traj, int64_t samples, int32_t turn);
+
 /* Gridding (Sec. 3.1, preprocessing): z_j = F^H y_j on the R x R field of view,
  * z_j(r) = (1/R) sum_s y_{j,s} exp(+i 2 pi k_s . r).
  * d_traj [B][K][S_r][2], d_y [B][J][S] -> d_z [B][J][R][R].

@@ -551,6 +551,14 @@ int nlinv_psf_spokes(nlinv_plan plan, const float* d_traj, int32_t spokes, int32
   return build_turn(plan, d_traj, turn, (int)((long long)spokes * (plan->s.S / plan->p.K)));
 }
 
+int nlinv_psf_samples(nlinv_plan plan, const float* d_traj, int64_t samples, int32_t turn) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  if (turn < 0 || turn >= plan->s.U) return fail(plan, NLINV_E_ARG, "turn out of range [0, U)");
+  if (samples < 1 || samples > plan->s.S) return fail(plan, NLINV_E_ARG, "samples must be in [1, K * S_r]");
+  return build_turn(plan, d_traj, turn, (int)samples);
+}
+
 int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const int32_t* h_turn,
                nlinv_c64* d_z) {
   NLV_CHECK(check_plan(plan));

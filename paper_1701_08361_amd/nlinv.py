@@ -58,6 +58,7 @@ def load() -> ctypes.CDLL:
         "nlinv_set_stream": [_P, _P],
         "nlinv_psf": [_P, _P, _I],
         "nlinv_psf_spokes": [_P, _P, _I, _I],
+        "nlinv_psf_samples": [_P, _P, ctypes.c_int64, _I],
         "nlinv_grid": [_P, _P, _P, _P, _P],
         "nlinv_reconstruct": [_P, _P, _P, _P, _P, _I, _P, _P],
         "nlinv_reconstruct_frames": [_P, _I, _P, _P, _P, _P, _P, _P],
@@ -201,13 +202,18 @@ class Plan:
         return self.torch.empty(*shape, dtype=dtype or self.torch.complex64, device=self.device)
 
     # -- API -------------------------------------------------------------
-    def psf(self, traj, turn: int, spokes: Optional[int] = None):
+    def psf(self, traj, turn: int, spokes: Optional[int] = None, samples: Optional[int] = None):
         """PSF kernel and gridding table of `turn` from traj [K][S_r][2]; with
-        `spokes`, from its first `spokes` spokes only (nlinv_psf_spokes)."""
+        `spokes`, from its first `spokes` spokes only (nlinv_psf_spokes); with
+        `samples`, from its first `samples` samples (nlinv_psf_samples)."""
         torch = self.torch
         self._t(traj, torch.float32, (self.K, self.S_r, 2), "traj")
+        if spokes is not None and samples is not None:
+            raise ValueError("give spokes or samples, not both")
         self._stream_sync()
-        if spokes is None:
+        if samples is not None:
+            _check(self.lib.nlinv_psf_samples(self.handle, self._ptr(traj), int(samples), int(turn)), self.handle)
+        elif spokes is None:
             _check(self.lib.nlinv_psf(self.handle, self._ptr(traj), int(turn)), self.handle)
         else:
             _check(self.lib.nlinv_psf_spokes(self.handle, self._ptr(traj), int(spokes), int(turn)), self.handle)

@@ -90,5 +90,6 @@ def test_null_plan_rejected(lib):
     assert lib.nlinv_set_batch(None, 1) == nl.E_ARG
     assert lib.nlinv_psf(None, None, 0) == nl.E_ARG
     assert lib.nlinv_psf_spokes(None, None, 1, 0) == nl.E_ARG
+    assert lib.nlinv_psf_samples(None, None, 1, 0) == nl.E_ARG
     assert lib.nlinv_get_batch(None) == 0
     assert b"NULL" in lib.nlinv_last_error(None)

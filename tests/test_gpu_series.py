@@ -234,3 +234,52 @@ def test_uneven_spoke_counts_share_a_batch(torch):
         x2, i2, _ = both.reconstruct(z2, [t, U + t], xprev=x2, init=1 if f == 0 else 2, want_img=True)
         assert torch.equal(x2[0], xa[0]) and torch.equal(i2[0], ia[0]), f
         assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0]), f
+
+
+def test_uneven_resolutions_share_a_batch(torch):
+    """Image sides, coil counts and spoke counts all uneven in one launch: a
+    48 px, 3-coil, 7-spoke series runs on the 128 grid of a 64 px, 4-coil,
+    9-spoke batched plan (gamma = 4/3 for it, Sec. 3.2), its 7 x 96 samples
+    packed at the start of the plan's 9 x 128 layout (nlinv_psf_samples) and
+    its fourth channel zero.  It equals its own 48 px plan on the 128 grid bit
+    for bit (image, coil spectra; the extra channel stays exactly zero), and
+    the 64 px item equals its batch-1 plan."""
+    U, M, C = 2, 3, 5
+    (Na, Ja, Ka), (Nb, Jb, Kb) = (48, 3, 7), (64, 4, 9)
+    G = 2 * Nb
+    print_case("uneven resolutions", Na=Na, Ja=Ja, Ka=Ka, Nb=Nb, Jb=Jb, Kb=Kb, G=G, M=M, C=C)
+    sa = synth.real_time_series(seed=43, N=Na, J=Ja, J_phys=6, K=Ka, U=U, frames=2)
+    sb = synth.real_time_series(seed=44, N=Nb, J=Jb, J_phys=6, K=Kb, U=U, frames=2)
+    na, S = Ka * 2 * Na, Kb * 2 * Nb
+    pa = nl().Plan(Na, Ja, Ka, G=G, U=U, newton=M, cg=C)
+    pb = nl().Plan(Nb, Jb, Kb, U=U, newton=M, cg=C)
+    both = nl().Plan(Nb, Jb, Kb, U=2 * U, batch=2, newton=M, cg=C)   # turns 0..U-1: a, U..2U-1: b
+    assert (pa.R, pa.G) == (both.R, both.G)
+    ta = np.zeros((2, S, 2), np.float32)
+    ta[:, :na] = sa.traj.reshape(2, na, 2)
+    ta = ta.reshape(2, Kb, 2 * Nb, 2)
+    ya = np.zeros((2, Jb, S), np.complex64)
+    ya[:, :Ja, :na] = sa.y
+    for t in range(U):
+        both.psf(dev(torch, ta[t]), t, samples=na)
+        both.psf(dev(torch, sb.traj[t]), U + t)
+    with pytest.raises(nl().NlinvError):
+        both.psf(dev(torch, ta[0]), 0, samples=S + 1)
+    Xa = pa.X
+    xa = xb = x2 = None
+    for f in range(2):
+        t = int(sa.turn[f])
+        assert t == int(sb.turn[f])
+        za = pa.grid(dev(torch, sa.traj[f:f + 1]), dev(torch, sa.y[f:f + 1]), turns=[t])
+        zb = pb.grid(dev(torch, sb.traj[f:f + 1]), dev(torch, sb.y[f:f + 1]), turns=[t])
+        z2 = both.grid(dev(torch, np.stack([ta[f], sb.traj[f]])), dev(torch, np.stack([ya[f], sb.y[f]])),
+                       turns=[t, U + t])
+        assert torch.equal(z2[0, :Ja], za[0]) and not torch.any(z2[0, Ja:] != 0)
+        assert torch.equal(z2[1], zb[0])
+        xa, ia, _ = pa.reconstruct(za, [t], xprev=xa, init=1 if f == 0 else 2, want_img=True)
+        xb, ib, _ = pb.reconstruct(zb, [t], xprev=xb, init=1 if f == 0 else 2, want_img=True)
+        x2, i2, _ = both.reconstruct(z2, [t, U + t], xprev=x2, init=1 if f == 0 else 2, want_img=True)
+        assert torch.equal(x2[0, :Xa], xa[0]) and not torch.any(x2[0, Xa:] != 0), f
+        assert torch.equal(i2[0], ia[0]) and torch.equal(pa.crop(i2[0]), pa.crop(ia[0])), f
+        assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0]), f
+    print("uneven resolutions: bit for bit")
