@@ -68,6 +68,7 @@ enum {
   NLINV_E_WORKSPACE = -3,  /* workspace missing or too small               */
   NLINV_E_HIP = -4,        /* HIP runtime / launch error                   */
   NLINV_E_STATE = -5,      /* call order violated (e.g. PSF not computed)  */
+  NLINV_E_NONFINITE = -6,  /* NLINV_F_CHECK_FINITE: a result was NaN / Inf */
 };
 
 /* Plan flags.
@@ -82,8 +83,12 @@ enum {
  *   1e-3 bound at that size; the default does (about 2e-5).
  * NLINV_F_EXACT_GRID: nlinv_grid always forms the exact sum (see
  *   nlinv_grid); without it, calls that name the turns use Kaiser-Bessel
- *   gridding through per-turn tables. */
-enum { NLINV_F_FAST = 1, NLINV_F_EXACT_GRID = 2 };
+ *   gridding through per-turn tables.
+ * NLINV_F_CHECK_FINITE: after every nlinv_reconstruct /
+ *   nlinv_reconstruct_frames one more kernel checks the result x_hat for NaN
+ *   and infinity and sets a device flag (no host synchronisation); the next
+ *   nlinv_sync returns NLINV_E_NONFINITE if it is set, and clears it. */
+enum { NLINV_F_FAST = 1, NLINV_F_EXACT_GRID = 2, NLINV_F_CHECK_FINITE = 4 };
 
 /* Plan parameters.  nlinv_params_default fills the defaults noted here. */
 typedef struct {

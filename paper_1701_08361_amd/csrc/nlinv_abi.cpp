@@ -145,7 +145,8 @@ void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, COV, total;
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, COV, FLAG,
+      total;
 };
 
 int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
@@ -166,7 +167,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (p->batch < 1 || p->batch > nlv::MAXB) return bad(NLINV_E_ARG, "batch must be in [1, 64]");
   if (p->newton < 0 || p->newton > 1000) return bad(NLINV_E_ARG, "newton must be in [0, 1000]");
   if (p->cg < 1 || p->cg > 100000) return bad(NLINV_E_ARG, "cg must be in [1, 100000]");
-  if (p->flags & ~(NLINV_F_FAST | NLINV_F_EXACT_GRID)) return bad(NLINV_E_ARG, "unknown flag bits");
+  if (p->flags & ~(NLINV_F_FAST | NLINV_F_EXACT_GRID | NLINV_F_CHECK_FINITE)) return bad(NLINV_E_ARG, "unknown flag bits");
   if (!(p->alpha0 > 0.0) || !std::isfinite(p->alpha0)) return bad(NLINV_E_ARG, "alpha0 must be positive and finite");
   if (!(p->alpha_q > 0.0 && p->alpha_q <= 1.0)) return bad(NLINV_E_ARG, "alpha_q must be in (0, 1]");
   if (!(p->alpha_min >= 0.0) || !std::isfinite(p->alpha_min)) return bad(NLINV_E_ARG, "alpha_min must be >= 0");
@@ -245,6 +246,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->KBC = take(S.kb ? R * 4 : 0);
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
   L->COV = take((size_t)nlv::MAX_JP * nlv::MAX_JP * c16);
+  L->FLAG = take(sizeof(int));
   L->total = off;
   return NLINV_OK;
 }
@@ -488,6 +490,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.kbc = reinterpret_cast<float*>(base + L.KBC);
   w.KG = reinterpret_cast<float2*>(base + L.KG);
   w.cov = reinterpret_cast<double2*>(base + L.COV);
+  w.flag = reinterpret_cast<int*>(base + L.FLAG);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -513,6 +516,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
     e = hipMemcpyAsync(w.dinv, dinv.data(), dinv.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
   if (e == hipSuccess && s.kb)
     e = hipMemcpyAsync(w.kbc, kbc.data(), kbc.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(w.flag, 0, sizeof(int), plan->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) {
     std::string m = std::string("HIP error uploading tables: ") + hipGetErrorString(e);
@@ -659,6 +663,14 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   return NLINV_OK;
 }
 
+// With NLINV_F_CHECK_FINITE: flag non-finite values of a result (outside any
+// captured graph; the flag stays set until nlinv_sync reports it).
+static int check_finite(nlinv_plan plan, const float2* x, long long n) {
+  if (!(plan->p.flags & NLINV_F_CHECK_FINITE)) return NLINV_OK;
+  NLV_HIP(plan, nlv::launch_check_finite(plan->stream, x, n, plan->w.flag));
+  return NLINV_OK;
+}
+
 // Capture the launch sequence enqueued by `body` once per key and replay it.
 static int run_captured(nlinv_plan plan, std::vector<uintptr_t> key, const std::function<int()>& body) {
   key.push_back((uintptr_t)plan->s.B);
@@ -720,9 +732,11 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
     std::vector<uintptr_t> key = {0, (uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)init,
                                   (uintptr_t)d_img, (uintptr_t)co};
     for (int b = 0; b < plan->s.B; ++b) key.push_back((uintptr_t)turns.t[b]);
-    return run_captured(plan, std::move(key), body);
+    NLV_CHECK(run_captured(plan, std::move(key), body));
+  } else {
+    NLV_CHECK(body());
   }
-  return body();
+  return check_finite(plan, xh, (long long)plan->s.B * plan->s.X);
 }
 
 // Frames n0 .. n0+count-1 of one series under the relaxed temporal coupling.
@@ -791,9 +805,11 @@ int nlinv_reconstruct_frames(nlinv_plan plan, int32_t count, const nlinv_c64* d_
     std::vector<uintptr_t> key = {1, (uintptr_t)z, (uintptr_t)xp, (uintptr_t)xh, (uintptr_t)d_img,
                                   (uintptr_t)co};
     for (int b = 0; b < count; ++b) key.push_back((uintptr_t)turns.t[b]);
-    return run_captured(plan, std::move(key), body);
+    NLV_CHECK(run_captured(plan, std::move(key), body));
+  } else {
+    NLV_CHECK(body());
   }
-  return body();
+  return check_finite(plan, xh, (long long)count * plan->s.X);
 }
 
 int nlinv_set_batch(nlinv_plan plan, int32_t b) {
@@ -957,6 +973,16 @@ int nlinv_sync(nlinv_plan plan) {
   NLV_CHECK(check_plan(plan));
   NLV_HIP(plan, hipStreamSynchronize(plan->stream));
   NLV_HIP(plan, hipGetLastError());
+  if (plan->p.flags & NLINV_F_CHECK_FINITE) {
+    int flag = 0;
+    NLV_HIP(plan, hipMemcpyAsync(&flag, plan->w.flag, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
+    NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+    if (flag) {
+      NLV_HIP(plan, hipMemsetAsync(plan->w.flag, 0, sizeof(int), plan->stream));
+      NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+      return fail(plan, NLINV_E_NONFINITE, "a reconstruction since the last nlinv_sync produced non-finite values");
+    }
+  }
   return NLINV_OK;
 }
 

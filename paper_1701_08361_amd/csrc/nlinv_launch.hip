@@ -401,6 +401,18 @@ k_nudft_fwd(const float* __restrict__ traj, const float2* __restrict__ u, float2
 }
 
 
+// flag |= 1 when any of the n complex values is NaN or infinite (a NaN fails
+// the comparison, an infinity exceeds the largest float)
+__global__ void __launch_bounds__(VT)
+k_check_finite(const float2* __restrict__ x, long long n, int* __restrict__ flag) {
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * VT + threadIdx.x; i < n; i += (long long)gridDim.x * VT) {
+    const float2 v = x[i];
+    bad |= !(fabsf(v.x) <= 3.402823466e38f && fabsf(v.y) <= 3.402823466e38f);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -547,6 +559,13 @@ hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const floa
   if (e != hipSuccess || nsplit == 1) return e;
   const long long n = (long long)s.B * s.J * s.R * s.R;
   k_grid_reduce<<<(int)((n + VT - 1) / VT), VT, 0, st>>>(w.GS, z, n, nsplit);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(hipStream_t st, const float2* x, long long n, int* flag) {
+  const long long want = (n + VT - 1) / VT;
+  const int blocks = (int)(want < 1024 ? (want < 1 ? 1 : want) : 1024);
+  k_check_finite<<<blocks, VT, 0, st>>>(x, n, flag);
   return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnlinv.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "nlinv.h")
 
-OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5
+OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+F_FAST, F_EXACT_GRID, F_CHECK_FINITE = 1, 2, 4
 KT = {"none": 0, "toeplitz_rows": 1, "coil_cols": 2, "back_cols": 3, "cg_update": 4,
       "coil_rows": 5, "coilh_rows": 6, "grid": 7}
 

@@ -53,7 +53,7 @@ def test_workspace_grows_with_batch(lib):
     (dict(N=64, J=8, K=13, batch=65), nl.E_ARG),
     (dict(N=64, J=8, K=13, U=0), nl.E_ARG),
     (dict(N=64, J=8, K=13, cg=0), nl.E_ARG),
-    (dict(N=64, J=8, K=13, flags=4), nl.E_ARG),   # unknown flag bit
+    (dict(N=64, J=8, K=13, flags=8), nl.E_ARG),   # unknown flag bit
     (dict(N=64, J=8, K=13, alpha0=0.0), nl.E_ARG),
     (dict(N=64, J=8, K=13, alpha_q=1.5), nl.E_ARG),
     (dict(N=64, J=8, K=13, alpha_min=-1.0), nl.E_ARG),

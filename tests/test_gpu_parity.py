@@ -424,3 +424,32 @@ def test_batched_items_equal_plain_c2(torch, c2_oracle):
     xb, ib, _ = many.reconstruct(zb, [t] * 16, want_img=True)
     for b in (0, 7, 15):
         assert torch.equal(xb[b], x1[0]) and torch.equal(ib[b], i1[0]), b
+
+
+def test_check_finite_flag(torch):
+    """NLINV_F_CHECK_FINITE: a clean reconstruction syncs fine; a non-finite
+    input sample makes the next nlinv_sync report NLINV_E_NONFINITE once (the
+    flag is cleared by the report); without the flag nothing is checked."""
+    N, J, K = 32, 3, 5
+    print_case("check finite", N=N, J=J, K=K)
+    s = synth.single_frame(seed=9, N=N, J=J, K=K)
+    lib = nl()
+    plan = lib.Plan(N, J, K, newton=2, cg=3, flags=lib.F_CHECK_FINITE)
+    z = plan.grid(dev(torch, s.traj), dev(torch, s.y), turns=[0])
+    plan.reconstruct(z, [0])
+    plan.sync()
+    bad = z.clone()
+    bad[0, 1, 5, 7] = complex(float("nan"), 0.0)
+    plan.reconstruct(bad, [0])
+    with pytest.raises(lib.NlinvError) as ei:
+        plan.sync()
+    assert ei.value.code == lib.E_NONFINITE
+    plan.sync()                                   # reported once, then cleared
+    x, _, _ = plan.reconstruct(z, [0])
+    plan.sync()
+    assert bool(torch.isfinite(torch.view_as_real(x)).all())
+    plain = lib.Plan(N, J, K, newton=2, cg=3)
+    plain.psf(dev(torch, s.traj[0]), 0)
+    xb, _, _ = plain.reconstruct(bad, [0])
+    plain.sync()
+    assert not bool(torch.isfinite(torch.view_as_real(xb)).all())
