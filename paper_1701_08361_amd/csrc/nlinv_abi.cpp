@@ -21,10 +21,16 @@ using nlv::Bufs;
 using nlv::Partials;
 using nlv::Shape;
 
+namespace nlv {
+// flag |= 1 if any of the n complex values of x is not finite (nlinv_launch.hip)
+hipError_t launch_check_finite(hipStream_t st, const float2* x, long long n, int* flag);
+}  // namespace nlv
+
 struct nlinv_plan_s {
   nlinv_params p;
   Shape s;   // shape of the active batch (s.B <= p.batch)
   Bufs w;
+  int* flag = nullptr;   // workspace int set by the finiteness check (NLINV_F_CHECK_FINITE)
   const nlv::GTable* t = nullptr;
   hipStream_t stream = nullptr;
   std::vector<char> psf_valid;
@@ -490,7 +496,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.kbc = reinterpret_cast<float*>(base + L.KBC);
   w.KG = reinterpret_cast<float2*>(base + L.KG);
   w.cov = reinterpret_cast<double2*>(base + L.COV);
-  w.flag = reinterpret_cast<int*>(base + L.FLAG);
+  plan->flag = reinterpret_cast<int*>(base + L.FLAG);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -516,7 +522,7 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
     e = hipMemcpyAsync(w.dinv, dinv.data(), dinv.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
   if (e == hipSuccess && s.kb)
     e = hipMemcpyAsync(w.kbc, kbc.data(), kbc.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(w.flag, 0, sizeof(int), plan->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(plan->flag, 0, sizeof(int), plan->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) {
     std::string m = std::string("HIP error uploading tables: ") + hipGetErrorString(e);
@@ -667,7 +673,7 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
 // captured graph; the flag stays set until nlinv_sync reports it).
 static int check_finite(nlinv_plan plan, const float2* x, long long n) {
   if (!(plan->p.flags & NLINV_F_CHECK_FINITE)) return NLINV_OK;
-  NLV_HIP(plan, nlv::launch_check_finite(plan->stream, x, n, plan->w.flag));
+  NLV_HIP(plan, nlv::launch_check_finite(plan->stream, x, n, plan->flag));
   return NLINV_OK;
 }
 
@@ -975,10 +981,10 @@ int nlinv_sync(nlinv_plan plan) {
   NLV_HIP(plan, hipGetLastError());
   if (plan->p.flags & NLINV_F_CHECK_FINITE) {
     int flag = 0;
-    NLV_HIP(plan, hipMemcpyAsync(&flag, plan->w.flag, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
+    NLV_HIP(plan, hipMemcpyAsync(&flag, plan->flag, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
     NLV_HIP(plan, hipStreamSynchronize(plan->stream));
     if (flag) {
-      NLV_HIP(plan, hipMemsetAsync(plan->w.flag, 0, sizeof(int), plan->stream));
+      NLV_HIP(plan, hipMemsetAsync(plan->flag, 0, sizeof(int), plan->stream));
       NLV_HIP(plan, hipStreamSynchronize(plan->stream));
       return fail(plan, NLINV_E_NONFINITE, "a reconstruction since the last nlinv_sync produced non-finite values");
     }

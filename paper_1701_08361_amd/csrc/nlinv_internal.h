@@ -91,7 +91,6 @@ struct Bufs {
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
   double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
-  int* flag;      // [1] set to 1 by the finiteness check (NLINV_F_CHECK_FINITE)
   LaunchTiming* lt = nullptr;   // the plan's kernel-timer hook (host memory)
 };
 
@@ -161,8 +160,6 @@ hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const 
 // mode 1: (rho = 1, c = 0); 2: copy xprev [B][X]; 3: broadcast xprev [X] to every item
 hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);
 hipError_t launch_image(const Shape& s, hipStream_t st, const float2* xh, const float2* co, float* img);
-// flag |= 1 if any of the n complex values of x is not finite
-hipError_t launch_check_finite(hipStream_t st, const float2* x, long long n, int* flag);
 hipError_t launch_grid(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, const float2* y,
                        float2* z);
 hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, const float2* u,
