@@ -46,6 +46,12 @@ int main(void) {
   nlinv_params_default(&p); p.N = 64; p.J = 8; p.K = 13; p.flags = 64;
   bad += expect(nlinv_workspace_size(&p, &ws), NLINV_E_ARG, "unknown flag");
   bad += expect(nlinv_workspace_size(NULL, &ws), NLINV_E_ARG, "NULL params");
+  nlinv_params_default(&p); p.N = 64; p.J = 8; p.K = 13; p.col_tile = 2;
+  bad += expect(nlinv_workspace_size(&p, &ws), NLINV_E_ARG, "col_tile 2");
+  nlinv_params_default(&p); p.N = 64; p.J = 8; p.K = 13; p.G = 448;
+  bad += expect(nlinv_workspace_size(&p, &ws), NLINV_E_SIZE, "gamma > 2");
+  nlinv_params_default(&p); p.N = 160; p.J = 8; p.K = 13; p.G = 448; p.flags = NLINV_F_CHECK_FINITE;
+  bad += expect(nlinv_workspace_size(&p, &ws), NLINV_OK, "gamma 1.4, finiteness check");
   if (!nlinv_last_error(NULL) || strlen(nlinv_last_error(NULL)) == 0) bad += 1;
   /* plan creation fails on the workspace before touching the device */
   nlinv_params_default(&p); p.N = 64; p.J = 8; p.K = 13;
@@ -56,6 +62,8 @@ int main(void) {
   bad += expect(nlinv_sync(NULL), NLINV_E_ARG, "sync(NULL)");
   bad += expect(nlinv_set_graphs(NULL, 1), NLINV_E_ARG, "set_graphs(NULL)");
   bad += expect(nlinv_set_batch(NULL, 1), NLINV_E_ARG, "set_batch(NULL)");
+  bad += expect(nlinv_psf_samples(NULL, NULL, 1, 0), NLINV_E_ARG, "psf_samples(NULL)");
+  bad += expect(nlinv_psf_spokes(NULL, NULL, 1, 0), NLINV_E_ARG, "psf_spokes(NULL)");
   bad += expect(nlinv_plan_destroy(NULL), NLINV_E_ARG, "destroy(NULL)");
   printf("checks done, %d failed\n", bad);
   return bad != 0;
