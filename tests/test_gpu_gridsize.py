@@ -80,3 +80,55 @@ def test_lookup_table_is_measured_once_per_device(torch, tmp_path, monkeypatch):
     assert GS.GridLUT(path).table(nl, torch, J=2, K=5, grids=[128, 256]) == lut
     key = GS.GridLUT.key(torch.cuda.get_device_name(), GS.library_digest(nl), 2)
     assert GS.GridLUT(path).get(key) == lut
+
+
+def test_gamma_operators_and_relaxed_series(torch):
+    """gamma = 1.6 (40 px on the 128 grid): F, DF, DF^H against the oracle of
+    the same grid within the operator bar, and a 6-frame series under the
+    relaxed coupling h(n, m) (l = 1, groups of 3) within the image bar."""
+    from paper_1701_08361_amd import nlinv as nl
+    N, G, J, K, U, M, C, F, l, o = 40, 128, 3, 7, 2, 2, 5, 6, 1, 3
+    print(f"[case] gamma operators + relaxed series N={N} G={G} J={J} K={K} F={F}", flush=True)
+    ser = synth.real_time_series(seed=61, N=N, J=J, J_phys=5, K=K, U=U, frames=F)
+    g = O.Geometry.make(N, J, G)
+    one = nl.Plan(N, J, K, G=G)
+    x = synth.random_xhat(300, g.R, J, g.Gc)
+    dx = synth.random_xhat(301, g.R, J, g.Gc)
+    v = synth.random_samples(302, J, one.S)
+    tr = torch.from_numpy(ser.traj[0:1]).cuda()
+    t0 = ser.traj[0].astype(np.float64)
+    Fx = one.apply_F(tr, torch.from_numpy(x[None]).cuda()).cpu().numpy()[0]
+    DFu = one.apply_DF(tr, torch.from_numpy(x[None]).cuda(), torch.from_numpy(dx[None]).cuda()).cpu().numpy()[0]
+    DFHv = one.apply_DFH(tr, torch.from_numpy(x[None]).cuda(), torch.from_numpy(v[None]).cuda()).cpu().numpy()[0]
+    R2 = g.R * g.R
+    ref = O.DFH_hat(g, x, v, t0)
+    errs = [rel(Fx, O.F_hat(g, x, t0)), rel(DFu, O.DF_hat(g, x, dx, t0)),
+            rel(DFHv[:R2], ref[:R2]), rel(DFHv[R2:], ref[R2:])]
+    print("gamma operators rel:", ", ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) < 1e-4
+    one.close()
+
+    src = O.relaxed_sources(F, l, o)
+    zs = [O.grid(ser.y[f], ser.traj[f], g.R) for f in range(F)]
+    Ps = [O.psf_kernel(ser.traj[f], g.R, g.G) for f in range(F)]
+    refs = O.reconstruct_series(g, zs, Ps, src, newton=M, cg_iters=C)
+    plan = nl.Plan(N, J, K, G=G, U=U, batch=o, newton=M, cg=C)
+    plan.set_batch(1)
+    z = torch.cat([plan.grid(torch.from_numpy(ser.traj[f:f + 1]).cuda(), torch.from_numpy(ser.y[f:f + 1]).cuda(),
+                             turns=[int(ser.turn[f])]) for f in range(F)], 0)
+    plan.set_batch(o)
+    xs = torch.empty(F, plan.X, dtype=torch.complex64, device="cuda")
+    imgs = torch.empty(F, plan.R, plan.R, dtype=torch.float32, device="cuda")
+    n = 0
+    while n < F:
+        k = 1
+        while n + k < F and src[n + k] == src[n] and n > l:
+            k += 1
+        plan.reconstruct_frames(z[n:n + k], [int(t) for t in ser.turn[n:n + k]],
+                                xprev=xs[n - 1] if n > 0 else None, xhat=xs[n:n + k], img=imgs[n:n + k])
+        n += k
+    imgs = imgs.cpu().numpy()
+    worst = max(rel(imgs[f], O.image(g, refs[f])) for f in range(F))
+    print(f"gamma relaxed series: worst image rel {worst:.2e}")
+    assert worst < IMG_TOL
+    plan.close()
