@@ -26,16 +26,17 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("N,J,K,B,G", [(64, 8, 13, 3, 0), (160, 10, 15, 1, 0), (120, 3, 9, 2, 480)])
-def test_column_tiles_agree_bit_for_bit(torch, N, J, K, B, G):
+@pytest.mark.parametrize("N,J,K,B,G,flags", [(64, 8, 13, 3, 0, 0), (160, 10, 15, 1, 0, 0), (120, 3, 9, 2, 480, 0),
+                                             (64, 8, 13, 2, 0, 1)])    # float32 half-transformed grid
+def test_column_tiles_agree_bit_for_bit(torch, N, J, K, B, G, flags):
     from paper_1701_08361_amd import nlinv as nl
-    print(f"[case] column tiles N={N} J={J} K={K} B={B} G={G}", flush=True)
+    print(f"[case] column tiles N={N} J={J} K={K} B={B} G={G} flags={flags}", flush=True)
     s = [synth.single_frame(seed=20 + b, N=N, J=J, K=K) for b in range(B)]
     traj = torch.from_numpy(np.concatenate([f.traj for f in s])).cuda()
     y = torch.from_numpy(np.concatenate([f.y for f in s])).cuda()
     out = {}
     for tile in (0, 4, 8):
-        plan = nl.Plan(N, J, K, batch=B, newton=3, cg=6, G=G, col_tile=tile)
+        plan = nl.Plan(N, J, K, batch=B, newton=3, cg=6, G=G, col_tile=tile, flags=flags)
         z = plan.grid(traj, y, turns=[0] * B) if B == 1 else None
         if B > 1:
             plan.psf(traj[0].contiguous(), 0)
@@ -58,3 +59,25 @@ def test_column_tiles_agree_bit_for_bit(torch, N, J, K, B, G):
     assert e < 1e-3
     for t in out.values():
         t[3].close()
+
+
+def test_psf_of_all_samples_equals_psf(torch):
+    """nlinv_psf_samples with every sample builds the same PSF kernel and
+    gridding table as nlinv_psf: the reconstructions agree bit for bit."""
+    from paper_1701_08361_amd import nlinv as nl
+    N, J, K = 64, 4, 9
+    print(f"[case] psf samples = K * S_r N={N} J={J} K={K}", flush=True)
+    s = synth.single_frame(seed=31, N=N, J=J, K=K)
+    traj = torch.from_numpy(s.traj).cuda()
+    y = torch.from_numpy(s.y).cuda()
+    res = []
+    for samples in (None, K * 2 * N):
+        plan = nl.Plan(N, J, K, newton=2, cg=4)
+        plan.psf(traj[0].contiguous(), 0, samples=samples)
+        z = plan.grid(traj, y, turns=[0])
+        x, img, _ = plan.reconstruct(z, [0], want_img=True)
+        torch.cuda.synchronize()
+        res.append((z.cpu(), x.cpu(), img.cpu()))
+        plan.close()
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
