@@ -220,6 +220,74 @@ def test_winv_adjoint_pair():
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
+def _weight_closed_form(ky, kx, G):
+    """w(k) = (1 + 880 |k|^2)^16 at k = kappa / G (Fig. weight_func), written out
+    here rather than taken from the oracle."""
+    return (1.0 + 880.0 * (ky * ky + kx * kx) / float(G * G)) ** 16
+
+
+@pytest.mark.parametrize("N,G", [(8, 16), (12, 24), (8, 20)])
+def test_winv_of_a_spectral_spike_is_a_weighted_plane_wave(N, G):
+    """Closed form of the coil synthesis W^-1 (Sec. 2.2, change of variables
+    x_hat = W x; Fig. weight_func): a single coil coefficient c_hat = delta at
+    the centred frequency kappa gives, on the field of view,
+        c(r) = exp(+i 2 pi kappa . r / G) / (G w(kappa)),
+    because F_u^-1 carries 1/G per 2D transform and W divides by w, not w^2 or
+    sqrt(w).  Every frequency of the G_c x G_c block is checked, on an odd G_c
+    (G = 20) as well."""
+    R, G, Gc = O.sizes(N, G)
+    w = O.sobolev_weight(G, Gc)
+    cs = O.centred(R).astype(np.float64)
+    Y, X = np.meshgrid(cs, cs, indexing="ij")
+    worst = 0.0
+    for iy, ky in enumerate(O.centred(Gc)):
+        for ix, kx in enumerate(O.centred(Gc)):
+            chat = np.zeros((1, Gc, Gc), complex)
+            chat[0, iy, ix] = 1.0
+            got = O.winv(chat, G, R, w)[0]
+            ref = np.exp(2j * np.pi * (kx * X + ky * Y) / G) / (G * _weight_closed_form(ky, kx, G))
+            worst = max(worst, rel(got, ref))
+    assert worst < 1e-12
+
+
+def _dirichlet(d, R, G):
+    """sum over x = -floor(R/2) .. R - 1 - floor(R/2) of exp(-i 2 pi d x / G), by the geometric series."""
+    a = -(R // 2)
+    if d % G == 0:
+        return complex(R)
+    q = np.exp(-2j * np.pi * d / G)
+    return q ** a * (1.0 - q ** R) / (1.0 - q)
+
+
+@pytest.mark.parametrize("N,G", [(8, 16), (12, 24), (8, 20)])
+def test_winvh_of_a_plane_wave_closed_form(N, G):
+    """Closed form of W^-H (the adjoint coil synthesis of the normal-operator
+    equation, Sec. 2.2): for the plane wave v(r) = exp(+i 2 pi kappa0 . r / G) on
+    the field of view,
+        (W^-H v)(kappa) = D(kappa_y - kappa0_y) D(kappa_x - kappa0_x) / (G w(kappa))
+    with D the geometric sum over the R field-of-view coordinates; at kappa =
+    kappa0 this is R^2 / (G w(kappa0))."""
+    R, G, Gc = O.sizes(N, G)
+    w = O.sobolev_weight(G, Gc)
+    cs = O.centred(R).astype(np.float64)
+    Y, X = np.meshgrid(cs, cs, indexing="ij")
+    kc = O.centred(Gc)
+    wc = np.array([[_weight_closed_form(ky, kx, G) for kx in kc] for ky in kc])
+    worst = 0.0
+    for k0y in (kc[0], 0, kc[-1]):
+        for k0x in (kc[0], 1, kc[-1]):
+            v = np.exp(2j * np.pi * (k0x * X + k0y * Y) / G)
+            got = O.winvh(v[None], G, Gc, w)[0]
+            # undo the closed-form 1 / (G w) and compare with the geometric sums; the
+            # weights span 20 orders of magnitude, so the comparison is made on the
+            # unweighted values, whose rounding is relative to their peak R^2
+            dd = np.array([[_dirichlet(ky - k0y, R, G) * _dirichlet(kx - k0x, R, G) for kx in kc] for ky in kc])
+            worst = max(worst, np.abs(got * G * wc - dd).max() / (R * R))
+            iy, ix = list(kc).index(k0y), list(kc).index(k0x)
+            assert abs(got[iy, ix] - R * R / (G * wc[iy, ix])) < 1e-12 * abs(got[iy, ix])
+    assert worst < 1e-12
+
+
 # --------------------------------------------------------------------------
 # operator identities (Sec. 2.2: F = script-F o C, derivative and adjoint)
 # --------------------------------------------------------------------------
