@@ -106,34 +106,59 @@ def _series(args):
     return s.traj, s.y, s.turn, target
 
 
+def pool_map(fn, jobs, workers):
+    """fn over jobs in a fork pool that is closed and joined (the workers exit
+    on their own instead of being terminated)."""
+    if workers <= 1 or len(jobs) <= 1:
+        return [fn(a) for a in jobs]
+    pool = mp.get_context("fork").Pool(min(workers, len(jobs)))
+    try:
+        out = pool.map(fn, jobs)
+    finally:
+        pool.close()
+        pool.join()
+    return out
+
+
 def make_data(seeds, frames, workers):
     if workers > 1 and len(seeds) > 1:
-        ctx = mp.get_context("fork")
-        with ctx.Pool(min(workers, len(seeds))) as pool:
-            return pool.map(_series, [(s, frames, 1) for s in seeds])
+        return pool_map(_series, [(s, frames, 1) for s in seeds], workers)
     return [_series((s, frames, None)) for s in seeds]
 
 
-def kernel_bytes(kind: str, B: int, fast: bool, turns_distinct: int) -> float:
-    """Algorithmic HBM bytes of one launch of a kernel class (each input read
-    once, each output written once)."""
+def kernel_bytes(kind: str, B: int, turns_distinct: int = 1, grid_bytes: int = 8) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel class: each input read
+    once, each output written once, every complex array at complex64 size
+    (8 B), the half-transformed grid at `grid_bytes` per value (8: complex64,
+    the algorithmic size; 16: the float64 storage of the last Newton step)."""
     G, R, Gc = 2 * N, N, N // 2
-    s2 = 8 if fast else 16
-    if kind == "toeplitz_rows":      # U2 rows in + out, PSF kernel rows
+    s2 = grid_bytes
+    if kind in ("toeplitz_rows", "toeplitz_rows_f64"):   # grid rows in + out, PSF kernel rows
         return B * J * G * R * 2 * s2 + turns_distinct * G * G * 4
-    if kind == "coil_cols":          # U1 in, coil images + image + p in, U2 out
-        return B * J * (Gc * R * 16 + R * R * 8 + G * R * s2) + B * R * R * (8 + 16 + 16)
-    if kind == "back_cols":          # U2 in, coils in, PR out, U1 out
-        return B * J * (G * R * s2 + R * R * 8 + R * R * 8 + Gc * R * 16) + B * R * R * (8 + 16)
+    if kind == "coil_cols":          # coil rows in, coil images + image + direction in, grid out
+        return B * J * (Gc * R * 8 + R * R * 8 + G * R * s2) + B * R * R * (8 + 8 + 8)
+    if kind == "back_cols":          # grid in, coils in, PR out, coil rows out
+        return B * J * (G * R * s2 + R * R * 8 + R * R * 8 + Gc * R * 8) + B * R * R * (8 + 8)
     raise ValueError(kind)
 
 
-def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, graphs, img_store=None):
+def compulsory_bytes_per_cg() -> float:
+    """Compulsory bytes of one CG iteration of one item (complex64): read the
+    direction, the coil images, the image, the PSF kernel and the Sobolev
+    weights, write the operator output."""
+    G, R, Gc = 2 * N, N, N // 2
+    X = R * R + J * Gc * Gc
+    return X * 8 + J * R * R * 8 + R * R * 8 + G * G * 4 + Gc * Gc * 4 + X * 8
+
+
+def run_mode(torch, nl, data, B, steps, warmup, timer_kernels, kt_frames, graphs, img_store=None, flags=0,
+             cg_passes=0):
     """Advance B series by warmup + steps frames (timed), then kt_frames more
-    with HIP events around every launch of `timer_kernel`.  Returns per-step ms,
-    total ms of the timed steps, and the kernel timer reading (ms, launches).
-    img_store[n] (optional) receives the image of frame n of item 0."""
-    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=(1 if fast else 0), col_tile=COL_TILE)
+    per kernel class in `timer_kernels` with the class's launches timed by HIP
+    events.  Returns per-step ms, total ms of the timed steps, and
+    {class: (ms, launches)}.  img_store[n] (optional) receives the image of
+    frame n of item 0."""
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=flags, col_tile=COL_TILE, cg_passes=cg_passes)
     plan.set_graphs(graphs)
     import numpy as np
     traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()  # [F,B,K,S_r,2]
@@ -159,7 +184,10 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, g
 
     xprev = None
     bufs = [xa, xb]
-    for n in range(warmup):
+    # with HIP graphs, every (turn, buffer parity) argument set is captured
+    # before the clock starts, whatever the warm-up count
+    nwarm = max(warmup, 2 * U) if graphs else warmup
+    for n in range(nwarm):
         frame(n, xprev, bufs[n & 1])
         xprev = bufs[n & 1]
     torch.cuda.synchronize()
@@ -167,7 +195,7 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, g
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        n = warmup + i
+        n = nwarm + i
         ev[i][0].record()
         frame(n, xprev, bufs[n & 1])
         ev[i][1].record()
@@ -175,15 +203,16 @@ def run_mode(torch, nl, data, B, steps, warmup, fast, timer_kernel, kt_frames, g
     torch.cuda.synchronize()
     total_ms = (time.perf_counter() - t0) * 1e3
     per = [a.elapsed_time(b) for a, b in ev]
-    kt = (0.0, 0)
-    if timer_kernel and kt_frames > 0:
+    kt = {}
+    n = nwarm + steps
+    for kernel in (timer_kernels if kt_frames > 0 else []):
         # per-kernel HIP events need uncaptured launches; same kernels, same sizes
-        plan.timer_enable(timer_kernel)
+        plan.timer_enable(kernel)
         for i in range(kt_frames):
-            n = warmup + steps + i
             frame(n, xprev, bufs[n & 1])
             xprev = bufs[n & 1]
-        kt = plan.timer_read()
+            n += 1
+        kt[kernel] = plan.timer_read()
         plan.timer_enable("none")
     plan.close()
     return per, total_ms, kt
@@ -597,26 +626,94 @@ def pct(v, q):
     return v[k]
 
 
-def cpu_baseline(seconds_hint: float = 30.0):
-    """The FP64 oracle (as it stands) on frame 0 of the series: gridding + PSF
-    kernel + 7 x 20 IRGNM.  One frame is the bounded sample."""
+def roofline(kt_by_batch, head_batch):
+    """Roofline object of the Toeplitz row pass (the dominant kernel).
+
+    Per batch size B, from the HIP events carried in each launch's dispatch:
+    algorithmic bytes of one launch = B J G R (8 + 8) + G^2 4 (the grid rows
+    in and out at complex64 size, the PSF kernel rows once), divided by the
+    average launch duration; frac = that rate / 8 TB/s.  The headline is the
+    batch-`head_batch` launch; every batch size is listed on its own, never
+    blended.  The grid is stored in float64, so the kernel moves
+    `storage_factor` = 2 times the algorithmic bytes: `storage_gbs` is that
+    rate."""
+    by = {}
+    for B, kt in sorted(kt_by_batch.items()):
+        ms, n = kt.get("toeplitz_rows", (0.0, 0))
+        if not n:
+            continue
+        t = ms / n / 1e3
+        alg = kernel_bytes("toeplitz_rows", B, 1, 8)
+        moved = kernel_bytes("toeplitz_rows", B, 1, 16)
+        by[str(B)] = {"launches": n, "avg_launch_us": t * 1e6, "algorithmic_bytes": alg,
+                      "achieved": alg / t / 1e9, "frac": alg / t / 1e9 / HBM_PEAK_GBS,
+                      "storage_factor": moved / alg, "storage_gbs": moved / t / 1e9}
+    head = by.get(str(head_batch))
+    if head is None:
+        return None
+    meas = measured_traffic("toeplitz_rows")
+    traffic = meas.get(head_batch) if meas else None
+    return {"kernel": "toeplitz_rows", "batch": head_batch, "bound": "hbm", "achieved": head["achieved"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac"], "traffic": traffic,
+            "algorithmic_bytes_per_launch": head["algorithmic_bytes"], "avg_launch_us": head["avg_launch_us"],
+            "launches": head["launches"], "storage_factor": head["storage_factor"],
+            "storage_gbs": head["storage_gbs"], "by_batch": by}
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, on the host cores, on bounded samples:
+      all threads : frame 0 of the 160 px series (exact gridding, PSF kernel,
+                    7 x 20 IRGNM) -> `value` (frames/s);
+      one thread  : the first Newton step (1 of 7, 20 CG) of the same frame,
+                    scaled to frames/s by its share of the frame's operator
+                    applications;
+      64 px frame : the single 64 px, 8-coil, 13-spoke frame (7 x 10), in full,
+                    all threads and one thread."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import nlinv_oracle as O
     from paper_1701_08361_amd import synth
     s = synth.real_time_series(seed=2, N=N, J=J, J_phys=J_PHYS, K=K, U=U, frames=1)
     g = O.Geometry.make(N, J)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     t0 = time.perf_counter()
     z = O.grid(s.y[0], s.traj[0], g.R)
     P = O.psf_kernel(s.traj[0], g.R, g.G)
     x = O.reconstruct(g, z, P, newton=M, cg_iters=C)
     dt = time.perf_counter() - t0
     assert np.isfinite(x).all()
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.reconstruct(g, z, P, newton=1, cg_iters=C)
+        dt1_step = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.grid(s.y[0], s.traj[0], g.R)
+        O.psf_kernel(s.traj[0], g.R, g.G)
+        dt1_prep = time.perf_counter() - t0
+    dt1 = dt1_prep + M * dt1_step
+    f1 = synth.single_frame(seed=1, N=64, J=8, K=13)
+    g1 = O.Geometry.make(64, 8)
+
+    def c1():
+        t0 = time.perf_counter()
+        z1 = O.grid(f1.y[0], f1.traj[0], g1.R)
+        P1 = O.psf_kernel(f1.traj[0], g1.R, g1.G)
+        O.reconstruct(g1, z1, P1, newton=7, cg_iters=10)
+        return time.perf_counter() - t0
+    c1_all = min(c1() for _ in range(3))
+    with threadpool_limits(1):
+        c1_one = min(c1() for _ in range(3))
+    model = cpu_model()
     return {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 frame (frame 0 of the 160px 10ch series: exact gridding, PSF kernel, "
-                      f"7x20 IRGNM) in {dt:.1f} s, {threads} BLAS threads on {os.cpu_count()} host CPUs "
-                      f"({cpu_model()})"}
+            "sample": f"1 frame (frame 0 of the 160px 10ch series: exact gridding, PSF kernel, 7x20 IRGNM) in "
+                      f"{dt:.1f} s, {threads} BLAS threads on {os.cpu_count()} host CPUs ({model})",
+            "one_core": {"value": 1.0 / dt1, "unit": "frames/s", "cores": 1,
+                         "sample": f"gridding + PSF kernel ({dt1_prep:.1f} s) and Newton step 0 of 7 "
+                                   f"(20 CG, {dt1_step:.1f} s) of frame 0, one thread; frame = prep + 7 steps"},
+            "c1_64px": {"all_cores": {"value": 1.0 / c1_all, "unit": "frames/s", "cores": threads},
+                        "one_core": {"value": 1.0 / c1_one, "unit": "frames/s", "cores": 1},
+                        "sample": "the 64 px, 8-coil, 13-spoke frame (seed 1): exact gridding, PSF kernel, 7x10 "
+                                  "IRGNM; best of 3"}}
 
 
 def cpu_model() -> str:
@@ -636,14 +733,15 @@ def main():
     ap.add_argument("--steps", type=int, default=1000,
                     help="timed frames of the plain series (the 100-frame series repeats; >= 1000 for p99)")
     ap.add_argument("--warmup", type=int, default=10,
-                    help="untimed frames; >= 10 so every (turn, buffer) graph is captured before timing")
+                    help="untimed frames (with --graphs at least 2U, so that every (turn, buffer) graph is "
+                         "captured before timing)")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=40)
     ap.add_argument("--mode", choices=["both", "plain", "batched"], default="both")
-    ap.add_argument("--fast", action="store_true", help="float32 half-transformed grid (NLINV_F_FAST)")
-    ap.add_argument("--kernel", default="toeplitz_rows", help="kernel class timed for the roofline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-graphs", action="store_true", help="launch kernels one by one (no HIP graphs)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay HIP graphs of the launch sequence (off by default: the autotuner measured "
+                         "eager launches as fast or faster)")
     ap.add_argument("--kt-frames", type=int, default=3, help="frames with per-kernel event timing")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference kernel for HBM byte counters)")
@@ -653,7 +751,7 @@ def main():
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     ap.add_argument("--serve-slices", type=int, default=4, help="slices streamed in the serving run (0 = skip)")
     ap.add_argument("--serve-periods", type=int, default=250, help="timed frame periods per slice")
-    ap.add_argument("--hbm-batch", type=int, default=32,
+    ap.add_argument("--hbm-batch", type=int, default=64,
                     help="batch of an extra run whose working set exceeds the 256 MB Infinity Cache (0 = skip)")
     ap.add_argument("--serve-fps", type=float, default=30.0, help="frames/s per slice")
     ap.add_argument("--diff-steps", type=int, default=2,
@@ -662,11 +760,15 @@ def main():
                     help="timed periods of the streaming pipeline (4 slices, receive channels; 0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed steps of the mixed-size run (3 shapes, 16 series; 0 = skip)")
-    ap.add_argument("--autotune-frames", default="5,10,25,50",
-                    help="series lengths of the autotuning run (learning mode over all settings; '' = skip)")
+    ap.add_argument("--autotune-frames", default="",
+                    help="series lengths of an autotuning run (learning mode over all settings; '' = skip)")
     ap.add_argument("--col-tile", type=int, default=0, choices=[0, 4, 8],
                     help="columns per block of the CG column passes (0 = the library's choice)")
-    ap.add_argument("--grid-lut-reps", type=int, default=30,
+    ap.add_argument("--cg-passes-plain", type=int, default=4, choices=[0, 4, 6],
+                    help="CG iteration form of the batch-1 plans (4: folded, measured faster at batch 1)")
+    ap.add_argument("--cg-passes-batched", type=int, default=6, choices=[0, 4, 6],
+                    help="CG iteration form of the batched plans (6: fewer bytes, measured faster at batch 16)")
+    ap.add_argument("--grid-lut-reps", type=int, default=0,
                     help="applications timed per grid side for the grid-size lookup table (0 = skip)")
     args = ap.parse_args()
     global COL_TILE
@@ -687,30 +789,22 @@ def main():
     batch_data = (make_data(list(range(2, 2 + args.batch)), frames_batch, args.workers)
                   if args.mode != "plain" else None)
     mixed_data = None
-    if args.mixed_steps > 0 and args.mode == "both" and not args.fast:
+    if args.mixed_steps > 0 and args.mode == "both":
         frames_mixed = max(U, 2 * U + args.mixed_steps)
         seeds, jobs = 100, []
         for (n, j, k, ns) in MIXED:
             jobs.append([(seeds + q, frames_mixed, 1, n, j, k) for q in range(ns)])
             seeds += ns
         flat = [a for g in jobs for a in g]
-        if args.workers > 1:
-            with mp.get_context("fork").Pool(min(args.workers, len(flat))) as pool:
-                res = pool.map(_series, flat)
-        else:
-            res = [_series(a) for a in flat]
+        res = pool_map(_series, flat, args.workers)
         mixed_data, q = [], 0
         for (n, j, k, ns) in MIXED:
             mixed_data.append((n, j, k, res[q:q + ns]))
             q += ns
     raw_data = None
-    if args.pipeline_periods > 0 and args.mode == "both" and not args.fast:
+    if args.pipeline_periods > 0 and args.mode == "both":
         jobs = [(200 + q, 2 * U + 10, n, j, jp, k) for q, (n, j, jp, k) in enumerate(SLICES)]
-        if args.workers > 1:
-            with mp.get_context("fork").Pool(min(args.workers, len(jobs))) as pool:
-                raw_data = pool.map(_raw_series, jobs)
-        else:
-            raw_data = [_raw_series(a) for a in jobs]
+        raw_data = pool_map(_raw_series, jobs, args.workers)
     t_gen = time.perf_counter() - t_gen
 
     cpu = None if args.no_cpu else cpu_baseline()
@@ -732,31 +826,32 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    kbytes, kms, klaunch = 0.0, 0.0, 0
-    launches_by_batch, by_batch = {}, {}
+    flags = 0
+    KT_CLASSES = ["toeplitz_rows"]
+    kt_by_batch = {}                     # batch -> {class: (ms, launches)}
     out = {"metric": "frames/sec + p99 frame latency, 160px 10ch NLINV, batched vs plain, 1 GPU",
            "unit": "frames/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+           "vs_baseline": None, "dtype": "mixed", "data": "synthetic",
+           "precision": {"storage": "c64 (data, gridded data, unknowns x_hat, coil images, channel products, "
+                                    "PSF kernel f32)",
+                         "operator_passes": "f64 arithmetic (registers, LDS) and f64 intermediates (coil rows, "
+                                            "half-transformed grid)",
+                         "cg_state": "f64 vectors (h, r, p, q), f64 dot products and scalars, f64 Newton update"}}
     img_strict = None
     if plain_data is not None:
-        img_strict = torch.zeros(args.warmup + args.steps, N, N, dtype=torch.float32, device="cuda")
-        per, total, (tms, tl) = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, args.fast, args.kernel,
-                                         args.kt_frames, not args.no_graphs, img_store=img_strict)
+        img_strict = torch.zeros(max(args.warmup, 2 * U) + args.steps, N, N, dtype=torch.float32, device="cuda")
+        per, total, kt = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, KT_CLASSES, args.kt_frames,
+                                  args.graphs, img_store=img_strict, flags=flags, cg_passes=args.cg_passes_plain)
         fps = args.steps / (total / 1e3)
         out.update({"value": fps, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps,
-                    "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}})
-        kbytes += tl * kernel_bytes(args.kernel, 1, args.fast, 1)
-        kms += tms
-        klaunch += tl
-        launches_by_batch[1] = tl
-        if tl:
-            by_batch["1"] = {"avg_launch_us": tms / tl * 1e3,
-                             "achieved": kernel_bytes(args.kernel, 1, args.fast, 1) / (tms / tl / 1e3) / 1e9}
-    if plain_data is not None and args.relaxed_o > 0 and not args.fast:
+                    "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)},
+                    "effective_gbs": 1 * M * (C + 2) * compulsory_bytes_per_cg() / (total / args.steps / 1e3) / 1e9})
+        kt_by_batch[1] = kt
+    if plain_data is not None and args.relaxed_o > 0 and True:
         l, o = args.relaxed_l, args.relaxed_o
         img_rel = torch.zeros_like(img_strict)
         nfr, total, per_g, n_end = run_relaxed(torch, nl, plain_data, args.steps, args.warmup, l, o,
-                                               not args.no_graphs, img_store=img_rel)
+                                               args.graphs, img_store=img_rel)
         nmax = min(n_end, img_strict.shape[0])
         d = (img_rel[l + 1:nmax] - img_strict[l + 1:nmax]).flatten(1).norm(dim=1) / \
             img_strict[l + 1:nmax].flatten(1).norm(dim=1)
@@ -766,43 +861,36 @@ def main():
                           "image_rel_diff_vs_strict": {"median": pct(d, 50), "max": max(d), "frames": len(d)}}
     if batch_data is not None:
         B = args.batch
-        per, total, (tms, tl) = run_mode(torch, nl, batch_data, B, args.batch_steps, args.warmup, args.fast,
-                                         args.kernel, args.kt_frames, not args.no_graphs)
+        per, total, kt = run_mode(torch, nl, batch_data, B, args.batch_steps, args.warmup, KT_CLASSES,
+                                  args.kt_frames, args.graphs, flags=flags, cg_passes=args.cg_passes_batched)
         out["batched"] = {"batch": B, "steps": args.batch_steps, "fps": B * args.batch_steps / (total / 1e3),
                           "ms_per_step": total / args.batch_steps,
-                          "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)}}
-        kbytes += tl * kernel_bytes(args.kernel, B, args.fast, 1)
-        kms += tms
-        klaunch += tl
-        launches_by_batch[B] = launches_by_batch.get(B, 0) + tl
-        if tl:
-            by_batch[str(B)] = {"avg_launch_us": tms / tl * 1e3,
-                                "achieved": kernel_bytes(args.kernel, B, args.fast, 1) / (tms / tl / 1e3) / 1e9}
+                          "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)},
+                          "effective_gbs": B * M * (C + 2) * compulsory_bytes_per_cg() /
+                                           (total / args.batch_steps / 1e3) / 1e9}
+        kt_by_batch[B] = kt
         if plain_data is None:
             out.update({"value": out["batched"]["fps"], "steps": args.batch_steps, "warmup": args.warmup,
                         "ms_per_step": out["batched"]["ms_per_step"]})
     if batch_data is not None and args.hbm_batch > 0:
-        # working set of ~1 GB: the Toeplitz pass cannot be served from the last-level cache
+        # U2 of 64 items is 64 x 10 x 320 x 160 x 8 B = 262 MB (float32) / 524 MB (float64): the float64
+        # launches' working set exceeds the 256 MB Infinity Cache, so their traffic reaches HBM
         hb = args.hbm_batch
         data_hb = [batch_data[i % len(batch_data)] for i in range(hb)]
-        _, total_hb, (tms_hb, tl_hb) = run_mode(torch, nl, data_hb, hb, 3, args.warmup, args.fast, args.kernel,
-                                                2, not args.no_graphs)
-        if tl_hb:
-            out["hbm_check"] = {"batch": hb, "fps": hb * 3 / (total_hb / 1e3), "kernel": args.kernel,
-                                "avg_launch_us": tms_hb / tl_hb * 1e3,
-                                "achieved": kernel_bytes(args.kernel, hb, args.fast, 1) / (tms_hb / tl_hb / 1e3) / 1e9,
-                                "peak": HBM_PEAK_GBS}
-            out["hbm_check"]["frac"] = out["hbm_check"]["achieved"] / HBM_PEAK_GBS
-    if batch_data is not None and args.serve_slices > 0 and not args.fast:
+        _, total_hb, kt = run_mode(torch, nl, data_hb, hb, 2, 0, KT_CLASSES, 1, args.graphs, flags=flags,
+                                   cg_passes=args.cg_passes_batched)
+        kt_by_batch[hb] = kt
+        out["hbm_check"] = {"batch": hb, "fps": hb * 2 / (total_hb / 1e3)}
+    if batch_data is not None and args.serve_slices > 0 and True:
         S = min(args.serve_slices, len(batch_data))
         serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods}
         for policy in ("plain", "batched"):
             lat, nfr, wall = run_serving(torch, nl, batch_data, S, args.serve_periods, 1e3 / args.serve_fps, policy,
-                                         not args.no_graphs)
+                                         args.graphs)
             serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
-    if plain_data is not None and args.diff_steps > 0 and not args.fast:
+    if plain_data is not None and args.diff_steps > 0 and True:
         fwd, tot, grads = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
         out["differentiation"] = {
             "form": "unrolled IRGNM, 5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
@@ -816,24 +904,24 @@ def main():
                          "reconstruction (7 x 20) -> image to host"}
         for name, shared in (("shared_streams", True), ("per_slice_streams", False)):
             lat, wall = run_pipeline(torch, raw_data, args.pipeline_periods, 1e3 / args.serve_fps, shared,
-                                     not args.no_graphs)
+                                     args.graphs)
             pipe[name] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                           "fps": len(lat) / (wall / 1e3)}
         out["serving_pipeline"] = pipe
-    if plain_data is not None and args.autotune_frames and not args.fast:
+    if plain_data is not None and args.autotune_frames and True:
         out["autotune"] = run_autotune(torch, nl, plain_data, [int(f) for f in args.autotune_frames.split(",")],
-                                       not args.no_graphs)
-    if args.grid_lut_reps > 0 and not args.fast:
+                                       args.graphs)
+    if args.grid_lut_reps > 0 and True:
         out["grid_choice"] = run_grid_choice(torch, nl, args.grid_lut_reps)
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],
                  "frames_per_step": nfr}
         for name, conc in (("one_stream", False), ("streams", True)):
-            per = run_mixed(torch, nl, mixed_data, args.mixed_steps, 2 * U, conc, not args.no_graphs)
+            per = run_mixed(torch, nl, mixed_data, args.mixed_steps, 2 * U, conc, args.graphs)
             mixed[name] = {"fps": nfr / (sum(per) / len(per) / 1e3), "ms_per_step": {"p50": pct(per, 50),
                                                                                     "p99": pct(per, 99)}}
-        per = run_mixed_one_launch(torch, nl, mixed_data, args.mixed_steps, 2 * U, not args.no_graphs)
+        per = run_mixed_one_launch(torch, nl, mixed_data, args.mixed_steps, 2 * U, args.graphs)
         mixed["one_launch"] = {"fps": nfr / (sum(per) / len(per) / 1e3),
                                "ms_per_step": {"p50": pct(per, 50), "p99": pct(per, 99)},
                                "form": "all series in one batched plan on the largest grid (smaller image "
@@ -841,22 +929,12 @@ def main():
         out["mixed"] = mixed
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
-                     "plain_batch": 1, "batched_batch": args.batch, "fast_grid": bool(args.fast),
-                     "hip_graphs": not args.no_graphs,
+                     "plain_batch": 1, "batched_batch": args.batch, "cg_passes_plain": args.cg_passes_plain,
+                     "cg_passes_batched": args.cg_passes_batched,
+                     "hip_graphs": args.graphs,
                      "data_gen_s": round(t_gen, 1)}
-    if klaunch:
-        achieved = kbytes / (kms / 1e3) / 1e9
-        # measured HBM bytes per launch, averaged over the same launch mix as `achieved`
-        meas = measured_traffic(args.kernel) if not args.fast else None
-        traffic = None
-        if meas is not None and all(b in meas for b in launches_by_batch):
-            traffic = sum(n * meas[b] for b, n in launches_by_batch.items()) / klaunch
-        out["roofline"] = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "algorithmic_bytes_per_launch": kbytes / klaunch,
-                           "avg_launch_us": kms / klaunch * 1e3, "launches": klaunch,
-                           "launches_by_batch": {str(b): n for b, n in launches_by_batch.items()},
-                           "by_batch": by_batch}
+    if kt_by_batch:
+        out["roofline"] = roofline(kt_by_batch, args.batch if batch_data is not None else 1)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

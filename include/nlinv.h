@@ -69,26 +69,23 @@ enum {
   NLINV_E_HIP = -4,        /* HIP runtime / launch error                   */
   NLINV_E_STATE = -5,      /* call order violated (e.g. PSF not computed)  */
   NLINV_E_NONFINITE = -6,  /* NLINV_F_CHECK_FINITE: a result was NaN / Inf */
+  NLINV_E_BUDGET = -7,     /* the device's workspace budget is exhausted    */
 };
 
 /* Plan flags.
- * NLINV_F_FAST: store the half-transformed grid of the PSF convolution (the
- *   largest intermediate, [J][G][R] per item) in float32 instead of float64.
- *   Halves that buffer's HBM traffic; CG amplifies the extra rounding, so
- *   reconstructions drift further from the float64 reference (the default
- *   keeps every operator intermediate except the coil images and the
- *   per-channel products in float64).  At 160 px, 7 x 20 iterations the
- *   final image differs from the float64 reference by 3e-4 to 1.2e-3
- *   (relative L2, depending on rounding order): this mode does not hold a
- *   1e-3 bound at that size; the default does (about 2e-5).
  * NLINV_F_EXACT_GRID: nlinv_grid always forms the exact sum (see
  *   nlinv_grid); without it, calls that name the turns use Kaiser-Bessel
  *   gridding through per-turn tables.
  * NLINV_F_CHECK_FINITE: after every nlinv_reconstruct /
  *   nlinv_reconstruct_frames one more kernel checks the result x_hat for NaN
  *   and infinity and sets a device flag (no host synchronisation); the next
- *   nlinv_sync returns NLINV_E_NONFINITE if it is set, and clears it. */
-enum { NLINV_F_FAST = 1, NLINV_F_EXACT_GRID = 2, NLINV_F_CHECK_FINITE = 4 };
+ *   nlinv_sync returns NLINV_E_NONFINITE if it is set, and clears it.
+ * Precision (not a flag): every transform runs in float64 arithmetic with
+ * float64 intermediates; the CG vectors, inner products and scalars and the
+ * Newton update are float64; the data, the gridded data, the unknowns x_hat,
+ * the coil images and the per-channel products are stored as complex64.
+ * Bits 1 and 8 are not flags (rejected with NLINV_E_ARG). */
+enum { NLINV_F_EXACT_GRID = 2, NLINV_F_CHECK_FINITE = 4 };
 
 /* Plan parameters.  nlinv_params_default fills the defaults noted here. */
 typedef struct {
@@ -110,6 +107,14 @@ typedef struct {
   int32_t col_tile;   /* tile schedule: columns per block of the two column    */
                       /* passes of a CG iteration, 0 or 8 (default) or 4       */
                       /* (twice the blocks); results are identical bit for bit */
+  int32_t cg_passes;  /* form of a CG iteration: 6 = coil rows with the        */
+                      /* direction update, the four operator passes, the CG   */
+                      /* vector step; 4 = the direction update, W^-1 p and the */
+                      /* vector step folded into the operator's passes, with   */
+                      /* Re<p, q> from the spectrum (Parseval; two dependent   */
+                      /* kernels fewer, about 15 % more bytes); 0 (default) =  */
+                      /* 6.  Both forms are the same CG in exact arithmetic;   */
+                      /* they differ in rounding only                          */
 } nlinv_params;
 
 /* Fill `p` with the defaults above (N, K left 0).  Never fails for non-NULL p. */
@@ -117,6 +122,9 @@ int nlinv_params_default(nlinv_params* p);
 
 /* Validate `p` and return the workspace size in bytes.  Host-only: needs no GPU. */
 int nlinv_workspace_size(const nlinv_params* p, size_t* bytes);
+
+/* The same call under the name nlinv_plan_workspace_size. */
+int nlinv_plan_workspace_size(const nlinv_params* p, size_t* bytes);
 
 /* Derived sizes of a parameter set (host-only).  Any output may be NULL. */
 int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc,
@@ -130,6 +138,18 @@ int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc,
 int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace,
                       size_t ws_bytes, nlinv_plan* out);
 int nlinv_plan_destroy(nlinv_plan plan);
+
+/* Admission by device-memory budget (Sec. 3.1: several slices of a real-time
+ * pipeline share one GPU).  With budget_bytes > 0, nlinv_plan_create on HIP
+ * device `device` (0..63) fails with
+ * NLINV_E_BUDGET, before touching the device, when the new plan's workspace
+ * (nlinv_workspace_size) plus the workspaces of the live plans on that device
+ * would exceed budget_bytes; nlinv_plan_destroy returns a plan's share.
+ * budget_bytes = 0 (the default) removes the cap.  Lowering the budget below
+ * what is in use affects only later plans.  nlinv_budget_used reports the
+ * summed workspace bytes of the live plans on `device`.  Thread-safe; host-only. */
+int nlinv_set_budget(int32_t device, size_t budget_bytes);
+int nlinv_budget_used(int32_t device, size_t* used_bytes);
 int nlinv_set_stream(nlinv_plan plan, void* stream);
 
 /* PSF kernel of one turn (Sec. 2.2 footnote; Fig. flow: convolution with the

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,6 +25,8 @@ using nlv::Shape;
 namespace nlv {
 // flag |= 1 if any of the n complex values of x is not finite (nlinv_launch.hip)
 hipError_t launch_check_finite(hipStream_t st, const float2* x, long long n, int* flag);
+// p[0] = v by a one-thread kernel
+hipError_t launch_fill_int(hipStream_t st, int* p, int v);
 }  // namespace nlv
 
 struct nlinv_plan_s {
@@ -45,11 +48,19 @@ struct nlinv_plan_s {
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graph_cache;
   float2* xb = nullptr;   // [B][X] source frames of nlinv_reconstruct_frames
   std::vector<int2> kbn_host;   // per turn: grid points with short / long gridding rows
+  int device = 0;               // HIP device the plan was created on
+  size_t ws_need = 0;           // its workspace size (counted against the device's budget)
 };
 
 namespace {
 
 thread_local std::string g_err;   // errors not tied to a plan
+
+// Per-device admission budget of plan workspaces (nlinv_set_budget).
+constexpr int MAX_DEV = 64;
+std::mutex g_dev_mu;
+size_t g_budget[MAX_DEV] = {};       // 0: no cap
+size_t g_used[MAX_DEV] = {};         // summed workspace sizes of the live plans
 
 int fail(nlinv_plan plan, int code, const std::string& msg) {
   if (plan) plan->err = msg; else g_err = msg;
@@ -152,6 +163,7 @@ void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
   size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, COV, FLAG,
+      VR, VP, PDFP, PPP, SCAL,
       total;
 };
 
@@ -173,13 +185,14 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (p->batch < 1 || p->batch > nlv::MAXB) return bad(NLINV_E_ARG, "batch must be in [1, 64]");
   if (p->newton < 0 || p->newton > 1000) return bad(NLINV_E_ARG, "newton must be in [0, 1000]");
   if (p->cg < 1 || p->cg > 100000) return bad(NLINV_E_ARG, "cg must be in [1, 100000]");
-  if (p->flags & ~(NLINV_F_FAST | NLINV_F_EXACT_GRID | NLINV_F_CHECK_FINITE)) return bad(NLINV_E_ARG, "unknown flag bits");
+  if (p->flags & ~(NLINV_F_EXACT_GRID | NLINV_F_CHECK_FINITE)) return bad(NLINV_E_ARG, "unknown flag bits");
   if (!(p->alpha0 > 0.0) || !std::isfinite(p->alpha0)) return bad(NLINV_E_ARG, "alpha0 must be positive and finite");
   if (!(p->alpha_q > 0.0 && p->alpha_q <= 1.0)) return bad(NLINV_E_ARG, "alpha_q must be in (0, 1]");
   if (!(p->alpha_min >= 0.0) || !std::isfinite(p->alpha_min)) return bad(NLINV_E_ARG, "alpha_min must be >= 0");
   if (!(p->sob_a >= 0.0) || !(p->sob_l >= 0.0) || !std::isfinite(p->sob_a) || !std::isfinite(p->sob_l))
     return bad(NLINV_E_ARG, "Sobolev parameters must be finite and >= 0");
   if (p->col_tile != 0 && p->col_tile != 4 && p->col_tile != 8) return bad(NLINV_E_ARG, "col_tile must be 0, 4 or 8");
+  if (p->cg_passes != 0 && p->cg_passes != 4 && p->cg_passes != 6) return bad(NLINV_E_ARG, "cg_passes must be 0, 4 or 6");
 
   Shape& S = *s;
   S.B = p->batch;
@@ -201,9 +214,10 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (S.NX3 + S.NCI > st) st = S.NX3 + S.NCI;
   if (S.NCH > st) st = S.NCH;
   S.stride = st;
-  S.fast = (p->flags & NLINV_F_FAST) != 0;
   S.coltile = p->col_tile;
   S.gsplit = nlv::grid_nsplit(S.B, S.J, S.R);
+  S.NTB = (S.J * S.G + tab->row_lines - 1) / tab->row_lines;
+  S.NPP = S.J * S.R;
   // Kaiser-Bessel gridding tables: (W + 1)^2 entries per sample and turn; left
   // out (exact gridding only) when they would take more than 2 GiB
   S.kbe_stride = (long long)S.S * KB_TAPS * KB_TAPS;
@@ -226,7 +240,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->psf = take(Gs * Gs * c16);
   L->CO = take(B * J * R * R * c8);
   L->U1 = take(B * J * GC * R * c16);
-  L->U2 = take(B * J * Gs * R * (S.fast ? c8 : c16));
+  L->U2 = take(B * J * Gs * R * c16);
   L->PR = take(B * J * R * R * c8);
   L->IMG = take(B * J * R * R * c8);
   // partial gridding sums: enough for the split of every active batch size
@@ -253,6 +267,11 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
   L->COV = take((size_t)nlv::MAX_JP * nlv::MAX_JP * c16);
   L->FLAG = take(sizeof(int));
+  L->VR = take(B * J * GC * R * c16);
+  L->VP = take(B * J * GC * R * c16);
+  L->PDFP = take(B * (size_t)S.NTB * 8);
+  L->PPP = take(B * (size_t)S.NPP * 8);
+  L->SCAL = take(B * c16);
   L->total = off;
   return NLINV_OK;
 }
@@ -438,8 +457,17 @@ int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc, int6
   return NLINV_OK;
 }
 
-int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
-                      nlinv_plan* out) {
+// Returns a plan's budget share and frees it.
+static void release_plan(nlinv_plan plan) {
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    g_used[plan->device] -= std::min(g_used[plan->device], plan->ws_need);
+  }
+  delete plan;
+}
+
+static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
+                       nlinv_plan* out) {
   if (!out) return fail(nullptr, NLINV_E_ARG, "out is NULL");
   *out = nullptr;
   Shape s;
@@ -453,16 +481,36 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   if (ws_bytes < L.total)
     return fail(nullptr, NLINV_E_WORKSPACE,
                 "workspace too small: need " + std::to_string(L.total) + " bytes");
+  int dev = 0;
+  {
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(nullptr, e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEV) return fail(nullptr, NLINV_E_ARG, "device index beyond 63");
+  }
 
   nlinv_plan plan = new (std::nothrow) nlinv_plan_s;
   if (!plan) return fail(nullptr, NLINV_E_ARG, "out of host memory");
+  // admission against the device's workspace budget (released by destroy or
+  // by a failure below)
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_budget[dev] != 0 && g_used[dev] + L.total > g_budget[dev]) {
+      delete plan;
+      return fail(nullptr, NLINV_E_BUDGET,
+                  "device budget exceeded: " + std::to_string(g_used[dev]) + " of " +
+                      std::to_string(g_budget[dev]) + " bytes in use, the plan needs " + std::to_string(L.total));
+    }
+    g_used[dev] += L.total;
+  }
+  plan->device = dev;
+  plan->ws_need = L.total;
   plan->p = *p;
   plan->s = s;
   plan->stream = reinterpret_cast<hipStream_t>(stream);
   plan->psf_valid.assign(s.U, 0);
   plan->t = nlv::table_for(s.G);
   if (!plan->t) {
-    delete plan;
+    release_plan(plan);
     return fail(nullptr, NLINV_E_SIZE, "no kernels for this grid size");
   }
   char* base = static_cast<char*>(d_workspace);
@@ -497,6 +545,11 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
   w.KG = reinterpret_cast<float2*>(base + L.KG);
   w.cov = reinterpret_cast<double2*>(base + L.COV);
   plan->flag = reinterpret_cast<int*>(base + L.FLAG);
+  w.Vr = reinterpret_cast<double2*>(base + L.VR);
+  w.Vp = reinterpret_cast<double2*>(base + L.VP);
+  w.pdfp = reinterpret_cast<double*>(base + L.PDFP);
+  w.ppp = reinterpret_cast<double*>(base + L.PPP);
+  w.scal = reinterpret_cast<double2*>(base + L.SCAL);
 
   // FP64 host tables, stored as float32.
   std::vector<double2> tw(s.G);
@@ -522,14 +575,36 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, si
     e = hipMemcpyAsync(w.dinv, dinv.data(), dinv.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
   if (e == hipSuccess && s.kb)
     e = hipMemcpyAsync(w.kbc, kbc.data(), kbc.size() * sizeof(float), hipMemcpyHostToDevice, plan->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(plan->flag, 0, sizeof(int), plan->stream);
+  if (e == hipSuccess) e = nlv::launch_fill_int(plan->stream, plan->flag, 0);
   if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) {
     std::string m = std::string("HIP error uploading tables: ") + hipGetErrorString(e);
-    delete plan;
+    release_plan(plan);
     return fail(nullptr, NLINV_E_HIP, m);
   }
   *out = plan;
+  return NLINV_OK;
+}
+
+int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
+                      nlinv_plan* out) {
+  return create_plan(p, stream, d_workspace, ws_bytes, out);
+}
+
+int nlinv_plan_workspace_size(const nlinv_params* p, size_t* bytes) { return nlinv_workspace_size(p, bytes); }
+
+int nlinv_set_budget(int32_t device, size_t budget_bytes) {
+  if (device < 0 || device >= MAX_DEV) return fail(nullptr, NLINV_E_ARG, "device must be in [0, 63]");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  g_budget[device] = budget_bytes;
+  return NLINV_OK;
+}
+
+int nlinv_budget_used(int32_t device, size_t* used_bytes) {
+  if (device < 0 || device >= MAX_DEV) return fail(nullptr, NLINV_E_ARG, "device must be in [0, 63]");
+  if (!used_bytes) return fail(nullptr, NLINV_E_ARG, "used_bytes is NULL");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  *used_bytes = g_used[device];
   return NLINV_OK;
 }
 
@@ -538,7 +613,7 @@ int nlinv_plan_destroy(nlinv_plan plan) {
   for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
   for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
-  delete plan;
+  release_plan(plan);
   return NLINV_OK;
 }
 
@@ -602,6 +677,11 @@ int nlinv_grid(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_y, const
   return NLINV_OK;
 }
 
+// CG iteration form: the plan's cg_passes, or six passes (the form that moves
+// the fewest bytes; the choice does not depend on the batch size, so that an
+// item of a batch reconstructs the same bits as a plan of batch one)
+static int cg_passes(nlinv_plan plan) { return plan->p.cg_passes == 4 ? 4 : 6; }
+
 // Enqueue Newton steps m0 <= m < m1 of the reconstruction on plan->stream
 // (validated arguments); alpha_m follows the schedule from step 0.
 static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
@@ -617,46 +697,73 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   double alpha = plan->p.alpha0;
   for (int n = 0; n < m0; ++n) alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
   for (int n = m0; n < m1; ++n) {
+    const Shape& sg = s;
+    const int kt_toep = NLINV_KT_TOEPLITZ_ROWS;
     // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
-    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(s, w, st, xh); }));
+    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(sg, w, st, xh); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-              return plan->t->cols_fwd(s, w, st, 0, w.CO, xh, nullptr, w.U2);
+              return plan->t->cols_fwd(sg, w, st, 0, w.CO, xh, nullptr, w.U2);
             }));
-    NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
+    NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
     NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-              return plan->t->cols_back(s, w, st, 1, w.U2, w.CO, xh, z);
+              return plan->t->cols_back(sg, w, st, 1, w.U2, w.CO, xh, z);
             }));
     NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
-              return plan->t->coilh_rows(s, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
+              return plan->t->coilh_rows(sg, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
             }));
     NLV_HIP(plan, nlv::launch_cg_init(s, w, st, xh, xp, alpha));
 
     int ncur = s.NX3 + s.NCI, nprev = 0;
     const int C = plan->p.cg;
-    for (int i = 0; i < C; ++i) {
-      double2* pc = w.Pv[i & 1];
-      double2* pp = w.Pv[(i + 1) & 1];
-      const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
-      const bool upd = i > 0;
-      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
-                return plan->t->coil_rows_cg(s, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
-                                             upd ? pc : nullptr, sc);
-              }));
-      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-                return plan->t->cols_fwd(s, w, st, 1, w.CO, xh, pc, w.U2);
-              }));
-      NLV_HIP(plan, timed(plan, NLINV_KT_TOEPLITZ_ROWS, [&] { return plan->t->toep_rows(s, w, st, turns); }));
-      NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-                return plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr);
-              }));
-      NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
-                return plan->t->coilh_rows(s, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
-              }));
-      NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
-                return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh);
-              }));
-      nprev = ncur;
-      ncur = s.NCH;
+    if (cg_passes(plan) == 4) {
+      // four dependent kernels per CG iteration (see the four-pass section of
+      // nlinv_kernels.h): the direction update, the x-stage of W^-1 p and the
+      // CG vector updates ride in the operator's passes
+      for (int i = 0; i < C; ++i) {
+        double2* pn = w.Pv[i & 1];
+        const double2* po = w.Pv[(i + 1) & 1];
+        const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
+        const int first = i == 0, last = i == C - 1;
+        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+                  return plan->t->cg_cols_fwd(sg, w, st, xh, po, pn, sc, first);
+                }));
+        NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->cg_toep_rows(sg, w, st, turns); }));
+        const nlv::CGRed red{w.scal, w.pdfp, s.NTB, s.NTB, w.ppp, s.NPP, s.NPP, w.rr[i & 1], ncur, s.stride, alpha, 0};
+        NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] { return plan->t->cg_cols_back(sg, w, st, xh, red); }));
+        NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+                  return plan->t->cg_coilh(sg, w, st, pn, xh, alpha, w.rr[(i + 1) & 1], first, last);
+                }));
+        nprev = ncur;
+        ncur = s.NX3 + s.NRQ;
+      }
+    } else {
+      // six dependent kernels per CG iteration: coil rows with the direction
+      // update, the operator's four passes, the CG vector step
+      for (int i = 0; i < C; ++i) {
+        double2* pc = w.Pv[i & 1];
+        double2* pp = w.Pv[(i + 1) & 1];
+        const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
+        const bool upd = i > 0;
+        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
+                  return plan->t->coil_rows_cg(sg, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
+                                               upd ? pc : nullptr, sc);
+                }));
+        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+                  return plan->t->cols_fwd(sg, w, st, 1, w.CO, xh, pc, w.U2);
+                }));
+        NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
+        NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
+                  return plan->t->cols_back(sg, w, st, 0, w.U2, w.CO, xh, nullptr);
+                }));
+        NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+                  return plan->t->coilh_rows(sg, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
+                }));
+        NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
+                  return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh);
+                }));
+        nprev = ncur;
+        ncur = s.NCH;
+      }
     }
     alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
   }
@@ -984,7 +1091,7 @@ int nlinv_sync(nlinv_plan plan) {
     NLV_HIP(plan, hipMemcpyAsync(&flag, plan->flag, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
     NLV_HIP(plan, hipStreamSynchronize(plan->stream));
     if (flag) {
-      NLV_HIP(plan, hipMemsetAsync(plan->flag, 0, sizeof(int), plan->stream));
+      NLV_HIP(plan, nlv::launch_fill_int(plan->stream, plan->flag, 0));
       NLV_HIP(plan, hipStreamSynchronize(plan->stream));
       return fail(plan, NLINV_E_NONFINITE, "a reconstruction since the last nlinv_sync produced non-finite values");
     }

@@ -26,6 +26,19 @@ struct Partials {
   int stride;
 };
 
+// Scalars of the four-pass CG iteration, reduced by one extra block per item
+// of the column pass back: scal[b] = (Re<p, q>, rr) with
+// Re<p, q> = sum of the Toeplitz partials (||DF p||^2) + alpha * sum of the
+// direction partials (|p|^2) and rr = sum of the residual partials.
+struct CGRed {
+  double2* scal;                      // [B]; nullptr: no reduction
+  const double* dfp; int ndfp, sdfp;  // Toeplitz-pass partials, count and stride per item
+  const double* pp; int npp, spp;     // direction partials
+  const double* rr; int nrr, srr;     // residual partials
+  double alpha;
+  int nbase;                          // blocks of the pass itself; block nbase + b reduces item b
+};
+
 // Sizes shared by all launches of a plan.
 struct Shape {
   int B, J, G, R, GC, S, U;
@@ -36,11 +49,12 @@ struct Shape {
   int NCI;             // rho-block chunks (ceil(R*R / CHUNK))
   int NCH;             // vector chunks (ceil(X / CHUNK))
   int stride;          // partial slots per item
-  bool fast;           // U2 stored in float32 instead of float64
   int gsplit;          // sample-range split of the gridding kernel (1 = none)
   bool kb;             // Kaiser-Bessel gridding tables present
   long long kbe_stride;  // table entries per turn
   int coltile;         // tile schedule of cols_fwd / cols_back: 0 (the library's), 4 or 8
+  int NTB;             // Toeplitz-pass blocks per item of the four-pass CG (ceil(J G / row_lines))
+  int NPP;             // direction-partial slots per item (J * R: one per channel and column)
 };
 
 // Columns per block of a CG column pass (the plan's tile schedule; the
@@ -73,7 +87,7 @@ struct Bufs {
   double2* psf;   // [G][G] scratch for the PSF build
   float2* CO;     // [B][J][R][R] coil images c_j
   double2* U1;    // [B][J][GC][R] coil-spectrum lines (also the adjoint output)
-  void* U2;       // [B][J][G][R] half-transformed grid, double2 (or float2 when fast)
+  void* U2;       // [B][J][G][R] half-transformed grid (double2)
   float2* PR;     // [B][J][R][R] per-channel conj(c_j) t_j
   float2* IMG;    // [B][J][R][R] image-space scratch
   float2* GS;     // [gsplit][B][J][R][R] partial gridding sums (gsplit > 1 only)
@@ -91,6 +105,11 @@ struct Bufs {
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
   double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
+  double2* Vr;    // [B][J][GC][R] x-stage of W^-1 applied to the residual's coil block
+  double2* Vp;    // [B][J][GC][R] the same for the CG direction (carried by linearity)
+  double* pdfp;   // [B][NTB] Toeplitz-pass partials ||DF p||^2
+  double* ppp;    // [B][NPP] direction partials |p|^2
+  double2* scal;  // [B] (Re<p, q>, rr) of the current CG iteration
   LaunchTiming* lt = nullptr;   // the plan's kernel-timer hook (host memory)
 };
 
@@ -136,6 +155,16 @@ struct GTable {
   hipError_t (*coilh_rows)(const Shape&, const Bufs&, hipStream_t, int mode, const double2* pv,
                            const float2* xh, const float2* xprev, double alpha, double2* out,
                            double2* out2);
+  // four-pass CG iteration (see nlinv_kernels.h): direction update and forward column
+  // pass (Pold -> Pnew, Vr/Vp -> U2, direction partials); the Toeplitz row pass with
+  // the Parseval partials; the column pass back (mode 0) with the scalar reduction;
+  // the coil-adjoint rows with the CG vector updates (x += h on the last iteration)
+  hipError_t (*cg_cols_fwd)(const Shape&, const Bufs&, hipStream_t, const float2* xh, const double2* pold,
+                            double2* pnew, Partials sc, int first);
+  hipError_t (*cg_toep_rows)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns);
+  hipError_t (*cg_cols_back)(const Shape&, const Bufs&, hipStream_t, const float2* xh, const CGRed& red);
+  hipError_t (*cg_coilh)(const Shape&, const Bufs&, hipStream_t, const double2* pnew, float2* xh, double alpha,
+                         double* rr_next, int first, int last);
   // PSF kernel: 2D FFT of the embedded PSF (w.psf) -> P (real part x scale)
   hipError_t (*psf_fft)(const Shape&, const Bufs&, hipStream_t, float* P, double scale);
   // Kaiser-Bessel gridding of y [B][J][S] into z [B][J][R][R] with the turn tables

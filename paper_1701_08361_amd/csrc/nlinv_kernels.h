@@ -20,11 +20,11 @@
 // loaded and unwanted outputs are not stored.
 //
 // Precision: the transforms run in float64 registers and float64 LDS; the
-// half-transformed grid U2 is stored in float64 (default) or float32 (fast
-// plans), the small coil-row buffer U1 in float64, the coil images and the
-// per-channel products in float32.  CG iterates are far more sensitive to
-// rounding that differs from one operator application to the next than to a
-// fixed error of the operator, so the CG state (h, r, p, q) is float64 too.
+// half-transformed grid U2 and the small coil-row buffer U1 are stored in
+// float64, the coil images and the per-channel products in float32.  CG
+// iterates are far more sensitive to rounding that differs from one operator
+// application to the next than to a fixed error of the operator, so the CG
+// state (h, r, p, q) is float64 too.
 // CG scalars stay on the device as FP64 partial sums reduced in a fixed order
 // (deterministic, no atomics).
 #pragma once
@@ -92,11 +92,25 @@ __device__ __forceinline__ double block_sum_waves(double v, double* sh) {
   return s;
 }
 
+// s += p[i0], p[i0 + NT], ... (i < n) in that order, the loads of 8 terms issued
+// together so that their latencies overlap
+template <int NT>
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int i0, int n) {
+  constexpr int U = 8;
+  double s = 0.0;
+  for (int i = i0; i < n; i += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = i + NT * k < n ? p[i + NT * k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) s += v[k];
+  }
+  return s;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum_array_waves(const double* __restrict__ p, int n, double* sh) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
-  return block_sum_waves<NT>(s, sh);
+  return block_sum_waves<NT>(strided_sum<NT>(p, threadIdx.x, n), sh);
 }
 
 // Two block sums with one pair of barriers; sh holds at least 2 NT / 64 values.
@@ -125,10 +139,34 @@ __device__ __forceinline__ double2 block_sum2_waves(double u, double v, double* 
 template <int NT>
 __device__ __forceinline__ double2 block_sum2_arrays_waves(const double* __restrict__ p, int n,
                                                            const double* __restrict__ q, int m, double* sh) {
-  double s = 0.0, t = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
-  for (int i = threadIdx.x; i < m; i += NT) t += q[i];
-  return block_sum2_waves<NT>(s, t, sh);
+  return block_sum2_waves<NT>(strided_sum<NT>(p, threadIdx.x, n), strided_sum<NT>(q, threadIdx.x, m), sh);
+}
+
+// Sums of two partial arrays by the first wavefront of the block, broadcast to
+// every thread through sh[0..1]: the same order whatever the block size, so
+// that launches of different tile schedules reduce to the same bits.
+__device__ __forceinline__ double2 wave0_sum2_arrays(const double* __restrict__ p, int n,
+                                                     const double* __restrict__ q, int m, double* sh) {
+  __syncthreads();   // sh may still be read by a previous call
+  if (threadIdx.x < 64) {
+    double s = strided_sum<64>(p, threadIdx.x, n), t = strided_sum<64>(q, threadIdx.x, m);
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_down(s, off, 64);
+      t += __shfl_down(t, off, 64);
+    }
+    if (threadIdx.x == 0) {
+      sh[0] = s;
+      sh[1] = t;
+    }
+  }
+  __syncthreads();
+  return make_double2(sh[0], sh[1]);
+}
+
+__device__ __forceinline__ double beta_wave0(const Partials& sc, int b, double* sh) {
+  const double2 r = wave0_sum2_arrays(sc.cur + (size_t)b * sc.stride, sc.ncur, sc.prev + (size_t)b * sc.stride,
+                                      sc.nprev, sh);
+  return r.y != 0.0 ? r.x / r.y : 0.0;
 }
 
 template <int NT>
@@ -356,17 +394,29 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 // ---------------------------------------------------------------------------
 // toep_rows: along x, FFT (R inputs) -> x P(ky, kx) -> iFFT (R outputs), in place.
 // ---------------------------------------------------------------------------
-template <int G, class S2>
+// With PQ, the blocks are laid out per item (nbi blocks of RT lines over the
+// item's J G lines, the last one partial) and each block also writes the
+// partial sum_k P(k) |U(k)|^2 of its lines' spectra to part[b * pstride +
+// block]: summed over an item it is <u, F^H F u> = ||DF p||^2 (Parseval), the
+// operator part of Re<p, q> in the four-pass CG iteration.
+template <int G, class S2, bool PQ = false>
 __global__ void __launch_bounds__(row_threads<G>())
 k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
-            const double2* __restrict__ tw, int J, int nlines) {
+            const double2* __restrict__ tw, int J, int nlines, double* __restrict__ part, int pstride, int nbi) {
   using T = Team<G>;
   constexpr int R = G / 2, RT = row_lines<G>();
   __shared__ C lds[RT * T::LDSN];
+  __shared__ double sh[64];
   const int rl0 = (int)threadIdx.x / T::SIZE;
-  const int row0 = blockIdx.x * RT + rl0;
+  int row0 = blockIdx.x * RT + rl0;
+  bool inside = row0 < nlines;
+  if constexpr (PQ) {
+    const int ib = blockIdx.x / nbi, lb = blockIdx.x - ib * nbi;
+    row0 = ib * J * G + lb * RT + rl0;
+    inside = lb * RT + rl0 < J * G;
+  }
   // lanes past the last team, or of a team past the last line, only take part in barriers
-  const bool act = rl0 < RT && row0 < nlines;
+  const bool act = rl0 < RT && inside;
   const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
   const int row = act ? row0 : 0;
   const int ky = row % G, b = row / G / J;
@@ -386,11 +436,18 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
     const int ix = img_idx<G>(n);
     return ix < 0 ? czero<C>() : to_d(nt_load(line + ix));
   }, v);
+  double acc = 0.0;
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
+      if constexpr (PQ) acc += (double)pk[k1] * (v[k1].x * v[k1].x + v[k1].y * v[k1].y);
       v[k1] = cscale(v[k1], (double)pk[k1]);
     });
+  }
+  if constexpr (PQ) {
+    static_assert(row_threads<G>() == 64, "one wavefront per block");
+    const double s = block_sum_waves<64>(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)(blockIdx.x / nbi) * pstride + blockIdx.x % nbi] = s;
   }
   fsB<G, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
     const int ix = img_idx<G>(n);
@@ -407,10 +464,24 @@ template <int G, int TWC, int MODE, class S2>
 __global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
             const float2* __restrict__ z, const double2* __restrict__ tw, float2* __restrict__ PR,
-            double2* __restrict__ U4, int J, long long X) {
+            double2* __restrict__ U4, int J, long long X, CGRed red) {
   using T = Team<G>;
-  constexpr int R = G / 2, GC = G / 4, NT = R / TWC;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TWC, NTH = cols_threads<G, TWC>();
   __shared__ C lds[TWC * T::LDSC];
+  if constexpr (MODE == 0) {
+    // four-pass CG: one extra block per item, after the pass's own blocks,
+    // reduces the partials of the passes before it to (Re<p, q>, rr) in a
+    // fixed order while the pass runs (block-uniform branch)
+    if (red.scal && (int)blockIdx.x >= red.nbase) {
+      __shared__ double shr[2];
+      const int bi = (int)blockIdx.x - red.nbase;
+      const double2 d = wave0_sum2_arrays(red.dfp + (size_t)bi * red.sdfp, red.ndfp,
+                                          red.pp + (size_t)bi * red.spp, red.npp, shr);
+      const double2 r = wave0_sum2_arrays(red.rr + (size_t)bi * red.srr, red.nrr, red.rr, 0, shr);
+      if (threadIdx.x == 0) red.scal[bi] = make_double2(d.x + red.alpha * d.y, r.x);
+      return;
+    }
+  }
   const bool act = (int)threadIdx.x < TWC * T::SIZE;
   const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
@@ -473,7 +544,8 @@ __global__ void __launch_bounds__(row_threads<G>())
 k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
              const double2* __restrict__ pv, const float2* __restrict__ xh, const float2* __restrict__ xprev,
              const float2* __restrict__ PR, double alpha, double2* __restrict__ out, double2* __restrict__ out2,
-             double* __restrict__ part, int stride, int slot_off, int J, long long X, int nb, int nr) {
+             double* __restrict__ part, int stride, int slot_off, int J, long long X, int nb, int nr,
+             double2* __restrict__ vr) {
   using T = Team<G>;
   constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
   static_assert(NTH == 64, "the q_rho block count assumes one wavefront per block");
@@ -560,17 +632,287 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
           const double2 bv = make_double2(w.x - alpha * ((double)xv[k1].x - xpv[k1].x),
                                           w.y - alpha * ((double)xv[k1].y - xpv[k1].y));
           out[e] = bv;
-          out2[e] = bv;
+          if (out2) out2[e] = bv;
           acc += bv.x * bv.x + bv.y * bv.y;
+          v[k1] = cscale(bv, (double)wv[k1]);   // input of the x-stage of W^-1 b
         } else {
           out[e] = w;
         }
+      } else if constexpr (MODE == 1) {
+        v[k1] = czero<C>();
       }
     });
+  }
+  if constexpr (MODE == 1) {
+    // x-stage of W^-1 applied to the right-hand side's coil row: the first
+    // residual's row transform of the four-pass CG iteration
+    if (vr) {
+      double2* o = vr + ((size_t)bj * GC + i) * R;
+      fsB<G, +1, SET_COIL, SET_IMG>(tl, lds + rl * T::LDSN, tw, v, [&](int n, C val) {
+        const int ix = img_idx<G>(n);
+        if (ix >= 0) o[ix] = val;
+      });
+    }
   }
   if constexpr (MODE != 2) {
     const double s = block_sum_waves<NTH>(acc, sh);
     if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + chunk] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Four-pass CG iteration.  The direction update, the coil synthesis of the
+// direction and the CG vector updates are folded into the passes of the
+// operator, so that one iteration is four dependent kernels instead of six:
+//   cg_cols_fwd : beta = rr_i / rr_{i-1}; p_i = r_i + beta p_{i-1} (image block
+//                 written by the channel-0 blocks, coil row i by the lanes of
+//                 columns 2i and 2i + 1); the x-stage of W^-1 p_i by linearity,
+//                 V_p = V_r + beta V_p (V_r: x-stage of W^-1 r_i from the pass
+//                 before); y-iFFT -> dc, u = c dp_rho + rho dc, y-FFT -> U2;
+//                 partials |p_i|^2, one per channel and column
+//   toep_rows   : the plain pass plus the partials sum_k P(k)|U(k)|^2, which sum
+//                 to ||DF p_i||^2 = <u, F^H F u> (Parseval)
+//   cols_back   : the plain pass; the first block of each item reduces
+//                 Re<p, q> = ||DF p||^2 + alpha |p|^2 and rr_i
+//   cg_coilh    : a = rr_i / Re<p, q>; x-FFT (W^-H) -> q = W^-H(..) + alpha p_i,
+//                 h += a p_i, r_{i+1} = r_i - a q, the x-stage of W^-1 r_{i+1}
+//                 -> V_r; the image block q_rho = sum_j PR_j + alpha p_rho
+//                 likewise; partials |r_{i+1}|^2.  Last iteration: x += h.
+// Re<p, q> comes from the spectrum instead of the vector q, so a is known
+// before q is formed; in exact arithmetic both are the same number.
+// ---------------------------------------------------------------------------
+
+template <int G, int TWC, class S2>
+__global__ void __launch_bounds__((cols_threads<G, TWC>()))
+k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const float2* __restrict__ co,
+              const float2* __restrict__ xh, const double2* __restrict__ Rv, const double2* __restrict__ Pold,
+              double2* __restrict__ Pnew, Partials sc, double* __restrict__ ppp, int spp,
+              const double2* __restrict__ tw, S2* __restrict__ U2, int J, long long X, int first) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NT = R / TWC, NTH = cols_threads<G, TWC>();
+  __shared__ C lds[TWC * T::LDSC];
+  __shared__ double sh[2 * (NTH / 64)];
+  const bool act = (int)threadIdx.x < TWC * T::SIZE;
+  const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
+  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
+  const int x = tile * TWC + col;
+  C* L = lds + col * T::LDSC;
+
+  // x-stage rows of r_i and of p_{i-1} at this column, rho and the coil image
+  const size_t vo = (size_t)bj * GC * R + x;
+  C a[T::G2], vp[T::G2];
+  if (tl < T::G1) {
+    sfor<0, T::G2>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
+      a[n2] = czero<C>();
+      vp[n2] = czero<C>();
+      if constexpr (cls_n<G, SET_COIL, n2>() != NEVER) {
+        const int i = coil_idx<G>(tl + T::G1 * n2);
+        if (i >= 0) {
+          a[n2] = Vr[vo + (size_t)i * R];
+          if (!first) vp[n2] = Vp[vo + (size_t)i * R];
+        }
+      }
+    });
+  }
+  const float2* rho = xh + (size_t)b * X;
+  const float2* cj = co + (size_t)bj * R * R;
+  float2 rv[T::G1], cv[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+        const int iy = img_idx<G>(T::G2 * k1 + tl);
+        if (iy >= 0) {
+          const size_t e = (size_t)iy * R + x;
+          rv[k1] = rho[e];
+          cv[k1] = cj[e];
+        }
+      }
+    });
+  }
+  const double beta = first ? 0.0 : beta_wave0(sc, b, sh);
+  // V_p = V_r + beta V_p: the x-stage of W^-1 p_i, kept for the next iteration
+  if (tl < T::G1) {
+    sfor<0, T::G2>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
+      if constexpr (cls_n<G, SET_COIL, n2>() != NEVER) {
+        const int i = coil_idx<G>(tl + T::G1 * n2);
+        if (i >= 0) {
+          a[n2] = make_double2(a[n2].x + beta * vp[n2].x, a[n2].y + beta * vp[n2].y);
+          Vp[vo + (size_t)i * R] = a[n2];
+        }
+      }
+    });
+  }
+  C v[T::G1];
+  fsA_regs<G, +1, SET_IMG>(tl, L, tw, a, v);
+  // image block of p_i at this column (written once, by the channel-0 blocks)
+  double acc = 0.0;
+  const size_t xb = (size_t)b * X;
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int iy = img_idx<G>(T::G2 * k1 + tl);
+      C u = czero<C>();
+      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) {
+        const size_t e = xb + (size_t)iy * R + x;
+        double2 dp = Rv[e];
+        if (!first) {
+          const double2 po = Pold[e];
+          dp = make_double2(dp.x + beta * po.x, dp.y + beta * po.y);
+        }
+        if (j == 0) {
+          Pnew[e] = dp;
+          acc += dp.x * dp.x + dp.y * dp.y;
+        }
+        u = cadd(cmul(to_d(cv[k1]), dp), cmul(to_d(rv[k1]), v[k1]));
+      }
+      v[k1] = u;
+    });
+  }
+  S2* o = U2 + (size_t)bj * G * R + x;
+  fsB<G, -1, SET_IMG, SET_ALL>(tl, L, tw, v, [&](int n, C val) { nt_store(o + (size_t)n * R, store_as<S2>(val)); });
+  // coil block of p_i: column x takes half of coil row x / 2 (R = 2 G_c), and
+  // every partial below covers one column, so the sums do not depend on the
+  // tile schedule (every schedule gives the same bits)
+  if (act) {
+    const int i = x >> 1;
+    const size_t e0 = xb + (size_t)R * R + ((size_t)j * GC + i) * GC + (x & 1) * (GC / 2);
+    for (int m = tl; m < GC / 2; m += T::SIZE) {
+      double2 p = Rv[e0 + m];
+      if (!first) {
+        const double2 po = Pold[e0 + m];
+        p = make_double2(p.x + beta * po.x, p.y + beta * po.y);
+      }
+      Pnew[e0 + m] = p;
+      acc += p.x * p.x + p.y * p.y;
+    }
+  }
+  // |p_i|^2 partial of each column: its lanes in lane order
+  __shared__ double shc[NTH];
+  shc[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < TWC) {
+    double sp = 0.0;
+    for (int t = 0; t < T::SIZE; ++t) sp += shc[t * TWC + threadIdx.x];
+    ppp[(size_t)b * spp + (size_t)j * R + tile * TWC + threadIdx.x] = sp;
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(row_threads<G>())
+k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const double2* __restrict__ tw,
+           const double2* __restrict__ Pn, const float2* __restrict__ PR, double2* __restrict__ H,
+           double2* __restrict__ Rv, float2* __restrict__ xh, double2* __restrict__ Vr,
+           const double2* __restrict__ scal, double alpha, double* __restrict__ rr_next, int stride, int J,
+           long long X, int nb, int nr, int first, int last) {
+  using T = Team<G>;
+  constexpr int R = G / 2, GC = G / 4, NTH = row_threads<G>(), RT = row_lines<G>();
+  static_assert(NTH == 64, "the image-block count assumes one wavefront per block");
+  __shared__ C lds[RT * T::LDSN];
+  __shared__ double sh[NTH];
+  const int b = blockIdx.x / (nb + nr), chunk = blockIdx.x - b * (nb + nr);
+  const double2 sv = scal[b];                        // (Re<p, q>, rr_i)
+  const double a = sv.x != 0.0 ? sv.y / sv.x : 0.0;
+  if (chunk >= nb) {   // block-uniform: image block, one pixel per lane
+    const int e = (chunk - nb) * NTH + (int)threadIdx.x;
+    double acc = 0.0;
+    if (e < R * R) {
+      const size_t ve = (size_t)b * X + e;
+      const double2 p = Pn[ve];
+      double qx = 0.0, qy = 0.0;
+      for (int j = 0; j < J; ++j) {
+        const float2 pr = PR[((size_t)b * J + j) * R * R + e];
+        qx += pr.x;
+        qy += pr.y;
+      }
+      qx += alpha * p.x;
+      qy += alpha * p.y;
+      double2 h = first ? make_double2(0.0, 0.0) : H[ve];
+      h = make_double2(h.x + a * p.x, h.y + a * p.y);
+      if (last) {
+        const float2 xv = xh[ve];
+        xh[ve] = make_float2((float)(xv.x + h.x), (float)(xv.y + h.y));
+      } else {
+        H[ve] = h;
+        double2 r = Rv[ve];
+        r = make_double2(r.x - a * qx, r.y - a * qy);
+        Rv[ve] = r;
+        acc = r.x * r.x + r.y * r.y;
+      }
+    }
+    if (!last) {
+      const double s = block_sum_waves<NTH>(acc, sh);
+      if (threadIdx.x == 0) rr_next[(size_t)b * stride + nb + (chunk - nb)] = s;
+    }
+    return;
+  }
+  const int rl0 = (int)threadIdx.x / T::SIZE, l0 = chunk * RT + rl0;
+  const bool act = rl0 < RT && l0 < J * GC;
+  const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
+  const int l = act ? l0 : 0;
+  const int i = l % GC, j = l / GC, bj = b * J + j;
+  const double2* line = U4 + ((size_t)bj * GC + i) * R;
+  const size_t base = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
+  const float* dw = dinv + i * GC;
+  float wv[T::G1];
+  double2 pvv[T::G1], hv[T::G1], rvv[T::G1];
+  float2 xv[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      if constexpr (cls_k<G, SET_COIL, k1>() != NEVER) {
+        const int ic = coil_idx<G>(T::G2 * k1 + tl);
+        if (ic >= 0) {
+          wv[k1] = dw[ic];
+          pvv[k1] = Pn[base + ic];
+          hv[k1] = first ? make_double2(0.0, 0.0) : H[base + ic];
+          if (last) xv[k1] = xh[base + ic];
+          else rvv[k1] = Rv[base + ic];
+        }
+      }
+    });
+  }
+  C* L = lds + rl * T::LDSN;
+  C v[T::G1];
+  fsA<G, -1, SET_IMG, SET_COIL>(tl, L, tw, [&](int n) -> C {
+    const int ix = img_idx<G>(n);
+    return ix < 0 ? czero<C>() : line[ix];
+  }, v);
+  double acc = 0.0;
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int ic = coil_idx<G>(T::G2 * k1 + tl);
+      C nv = czero<C>();
+      if (cls_k<G, SET_COIL, k1>() != NEVER && ic >= 0) {
+        const size_t e = base + ic;
+        const double2 w = cscale(v[k1], (double)wv[k1]);
+        const double2 p = pvv[k1];
+        const double2 q = make_double2(w.x + alpha * p.x, w.y + alpha * p.y);
+        const double2 h = make_double2(hv[k1].x + a * p.x, hv[k1].y + a * p.y);
+        if (last) {
+          xh[e] = make_float2((float)(xv[k1].x + h.x), (float)(xv[k1].y + h.y));
+        } else {
+          H[e] = h;
+          const double2 r = make_double2(rvv[k1].x - a * q.x, rvv[k1].y - a * q.y);
+          Rv[e] = r;
+          acc += r.x * r.x + r.y * r.y;
+          nv = cscale(r, (double)wv[k1]);   // input of the x-stage of W^-1 r_{i+1}
+        }
+      }
+      v[k1] = nv;
+    });
+  }
+  if (!last) {   // uniform
+    double2* o = Vr + ((size_t)bj * GC + i) * R;
+    fsB<G, +1, SET_COIL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
+      const int ix = img_idx<G>(n);
+      if (ix >= 0) o[ix] = val;
+    });
+    const double s = block_sum_waves<NTH>(acc, sh);
+    if (threadIdx.x == 0) rr_next[(size_t)b * stride + chunk] = s;
   }
 }
 
@@ -821,19 +1163,19 @@ struct GLaunch {
   }
   static hipError_t cols_fwd(const Shape& s, const Bufs& w, hipStream_t st, int mode, float2* co,
                              const float2* xh, const double2* pv, void* out) {
-    return s.fast ? cols_fwd_t<float2>(s, w, st, mode, co, xh, pv, out)
-                  : cols_fwd_t<double2>(s, w, st, mode, co, xh, pv, out);
+    return cols_fwd_t<double2>(s, w, st, mode, co, xh, pv, out);
   }
   template <class S2>
   static hipError_t toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
     constexpr int RT = row_lines<G>();
     const int nlines = s.B * s.J * s.G;
     const int blocks = (nlines + RT - 1) / RT;
-    return launch_timed(w, k_toep_rows<G, S2>, dim3(blocks), dim3(row_threads<G>()), 0, st, static_cast<S2*>(w.U2),
-                        (const float*)w.P, turns, (const double2*)w.tw, s.J, nlines);
+    return launch_timed(w, k_toep_rows<G, S2, false>, dim3(blocks), dim3(row_threads<G>()), 0, st,
+                        static_cast<S2*>(w.U2), (const float*)w.P, turns, (const double2*)w.tw, s.J, nlines,
+                        (double*)nullptr, 0, 1);
   }
   static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    return s.fast ? toep_rows_t<float2>(s, w, st, turns) : toep_rows_t<double2>(s, w, st, turns);
+    return toep_rows_t<double2>(s, w, st, turns);
   }
   template <class S2, int TWC>
   static hipError_t cols_back_k(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
@@ -842,13 +1184,13 @@ struct GLaunch {
     const int blocks = s.B * s.J * (s.R / TWC);
     switch (mode) {
       case 0: return launch_timed(w, k_cols_back<G, TWC, 0, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
-                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X, CGRed{});
       case 1: return launch_timed(w, k_cols_back<G, TWC, 1, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
-                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X, CGRed{});
       case 2: return launch_timed(w, k_cols_back<G, TWC, 2, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
-                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X, CGRed{});
       case 3: return launch_timed(w, k_cols_back<G, TWC, 3, S2>, dim3(blocks), dim3(TH), 0, st, in, co, xh, z,
-                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X);
+                                   (const double2*)w.tw, w.PR, w.U1, s.J, (long long)s.X, CGRed{});
       default: return hipErrorInvalidValue;
     }
   }
@@ -860,8 +1202,7 @@ struct GLaunch {
   }
   static hipError_t cols_back(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
                               const float2* co, const float2* xh, const float2* z) {
-    return s.fast ? cols_back_t<float2>(s, w, st, mode, in, co, xh, z)
-                  : cols_back_t<double2>(s, w, st, mode, in, co, xh, z);
+    return cols_back_t<double2>(s, w, st, mode, in, co, xh, z);
   }
   static hipError_t coilh_rows(const Shape& s, const Bufs& w, hipStream_t st, int mode, const double2* pv,
                                const float2* xh, const float2* xprev, double alpha, double2* out,
@@ -874,18 +1215,74 @@ struct GLaunch {
       case 0: return launch_timed(w, k_coilh_rows<G, 0>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
                                    (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
-                                   (long long)s.X, s.NX3, nr);
+                                   (long long)s.X, s.NX3, nr, (double2*)nullptr);
       case 1: return launch_timed(w, k_coilh_rows<G, 1>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
                                    (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
-                                   (long long)s.X, s.NX3, nr);
+                                   (long long)s.X, s.NX3, nr, w.Vr);
       case 2: return launch_timed(w, k_coilh_rows<G, 2>, dim3(blocks), dim3(TH_ROW1), 0, st,
                                    (const double2*)w.U1, (const float*)w.dinv, (const double2*)w.tw, pv, xh, xprev,
                                    (const float2*)w.PR, alpha, out, out2, part, s.stride, off, s.J,
-                                   (long long)s.X, s.NX3, nr);
+                                   (long long)s.X, s.NX3, nr, (double2*)nullptr);
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+  }
+  // four-pass CG iteration
+  template <class S2, int TWC>
+  static hipError_t cg_cols_fwd_k(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                                  const double2* pold, double2* pnew, Partials sc, int first) {
+    constexpr int TH = cols_threads<G, TWC>();
+    const int blocks = s.B * s.J * (s.R / TWC);
+    return launch_timed(w, k_cg_cols_fwd<G, TWC, S2>, dim3(blocks), dim3(TH), 0, st, (const double2*)w.Vr, w.Vp,
+                        (const float2*)w.CO, xh, (const double2*)w.Rv, pold, pnew, sc, w.ppp, s.NPP,
+                        (const double2*)w.tw, static_cast<S2*>(w.U2), s.J, (long long)s.X, first);
+  }
+  template <class S2>
+  static hipError_t cg_cols_fwd_t(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                                  const double2* pold, double2* pnew, Partials sc, int first) {
+    return col_tile(s, true) == 4 ? cg_cols_fwd_k<S2, 4>(s, w, st, xh, pold, pnew, sc, first)
+                                  : cg_cols_fwd_k<S2, TW>(s, w, st, xh, pold, pnew, sc, first);
+  }
+  static hipError_t cg_cols_fwd(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                                const double2* pold, double2* pnew, Partials sc, int first) {
+    return cg_cols_fwd_t<double2>(s, w, st, xh, pold, pnew, sc, first);
+  }
+  template <class S2>
+  static hipError_t cg_toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
+    return launch_timed(w, k_toep_rows<G, S2, true>, dim3(s.B * s.NTB), dim3(row_threads<G>()), 0, st,
+                        static_cast<S2*>(w.U2), (const float*)w.P, turns, (const double2*)w.tw, s.J,
+                        s.B * s.J * s.G, w.pdfp, s.NTB, s.NTB);
+  }
+  static hipError_t cg_toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
+    return cg_toep_rows_t<double2>(s, w, st, turns);
+  }
+  template <class S2, int TWC>
+  static hipError_t cg_cols_back_k(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                                   const CGRed& red) {
+    constexpr int TH = cols_threads<G, TWC>();
+    const int blocks = s.B * s.J * (s.R / TWC);
+    CGRed r = red;
+    r.nbase = blocks;   // one reducing block per item after the pass's blocks
+    return launch_timed(w, k_cols_back<G, TWC, 0, S2>, dim3(blocks + s.B), dim3(TH), 0, st, (const void*)w.U2,
+                        (const float2*)w.CO, xh, (const float2*)nullptr, (const double2*)w.tw, w.PR, w.U1, s.J,
+                        (long long)s.X, r);
+  }
+  template <class S2>
+  static hipError_t cg_cols_back_t(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
+                                   const CGRed& red) {
+    return col_tile(s, false) == 4 ? cg_cols_back_k<S2, 4>(s, w, st, xh, red) : cg_cols_back_k<S2, TW>(s, w, st, xh, red);
+  }
+  static hipError_t cg_cols_back(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh, const CGRed& red) {
+    return cg_cols_back_t<double2>(s, w, st, xh, red);
+  }
+  static hipError_t cg_coilh(const Shape& s, const Bufs& w, hipStream_t st, const double2* pnew, float2* xh,
+                             double alpha, double* rr_next, int first, int last) {
+    const int blocks = s.B * (s.NX3 + s.NRQ);
+    return launch_timed(w, k_cg_coilh<G>, dim3(blocks), dim3(TH_ROW1), 0, st, (const double2*)w.U1,
+                        (const float*)w.dinv, (const double2*)w.tw, pnew, (const float2*)w.PR, w.H, w.Rv, xh, w.Vr,
+                        (const double2*)w.scal, alpha, rr_next, s.stride, s.J, (long long)s.X, s.NX3, s.NRQ, first,
+                        last);
   }
   static hipError_t psf_fft(const Shape& s, const Bufs& w, hipStream_t st, float* P, double scale) {
     k_fft_rows_full<G><<<G / ROWS, TH_ROWS, 0, st>>>(w.psf, w.tw);
@@ -928,7 +1325,7 @@ struct GLaunch {
   }
   static hipError_t kb_grid(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns,
                             const float2* y, float2* z) {
-    return s.fast ? kb_grid_t<float2>(s, w, st, turns, y, z) : kb_grid_t<double2>(s, w, st, turns, y, z);
+    return kb_grid_t<double2>(s, w, st, turns, y, z);
   }
 };
 
@@ -936,7 +1333,8 @@ template <int G>
 constexpr GTable make_table() {
   return GTable{&GLaunch<G>::coil_rows, &GLaunch<G>::coil_rows_cg, &GLaunch<G>::cols_fwd,
                 &GLaunch<G>::toep_rows, &GLaunch<G>::cols_back, &GLaunch<G>::coilh_rows,
-                &GLaunch<G>::psf_fft, &GLaunch<G>::kb_grid, row_lines<G>()};
+                &GLaunch<G>::cg_cols_fwd, &GLaunch<G>::cg_toep_rows, &GLaunch<G>::cg_cols_back,
+                &GLaunch<G>::cg_coilh, &GLaunch<G>::psf_fft, &GLaunch<G>::kb_grid, row_lines<G>()};
 }
 
 }  // namespace nlv

@@ -413,9 +413,20 @@ k_check_finite(const float2* __restrict__ x, long long n, int* __restrict__ flag
   if (bad) atomicOr(flag, 1);
 }
 
+// p[0] = v (a one-thread fill kernel instead of hipMemsetAsync, so that the
+// clear is an ordinary kernel node wherever the call is enqueued)
+__global__ void k_fill_int(int* __restrict__ p, int v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_fill_int(hipStream_t st, int* p, int v) {
+  k_fill_int<<<1, 64, 0, st>>>(p, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
                           const float2* xprev, double alpha) {

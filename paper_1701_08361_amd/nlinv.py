@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnlinv.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "nlinv.h")
 
-OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
-F_FAST, F_EXACT_GRID, F_CHECK_FINITE = 1, 2, 4
+OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE, E_NONFINITE, E_BUDGET = 0, -1, -2, -3, -4, -5, -6, -7
+F_EXACT_GRID, F_CHECK_FINITE = 2, 4
 KT = {"none": 0, "toeplitz_rows": 1, "coil_cols": 2, "back_cols": 3, "cg_update": 4,
       "coil_rows": 5, "coilh_rows": 6, "grid": 7}
 
@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("newton", ctypes.c_int32), ("cg", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("alpha0", ctypes.c_double), ("alpha_q", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("sob_a", ctypes.c_double), ("sob_l", ctypes.c_double),
-                ("col_tile", ctypes.c_int32)]
+                ("col_tile", ctypes.c_int32), ("cg_passes", ctypes.c_int32)]
 
 
 _lib = None
@@ -54,7 +54,10 @@ def load() -> ctypes.CDLL:
         "nlinv_params_default": [ctypes.POINTER(Params)],
         "nlinv_workspace_size": [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
         "nlinv_sizes": [ctypes.POINTER(Params), _P, _P, _P, _P, _P],
+        "nlinv_plan_workspace_size": [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
         "nlinv_plan_create": [ctypes.POINTER(Params), _P, _P, ctypes.c_size_t, ctypes.POINTER(_P)],
+        "nlinv_set_budget": [_I, ctypes.c_size_t],
+        "nlinv_budget_used": [_I, ctypes.POINTER(ctypes.c_size_t)],
         "nlinv_plan_destroy": [_P],
         "nlinv_set_stream": [_P, _P],
         "nlinv_psf": [_P, _P, _I],
@@ -104,19 +107,32 @@ def _check(rc: int, plan=None):
 def make_params(N: int, J: int, K: int, S_r: int = 0, U: int = 1, batch: int = 1, newton: int = 7,
                 cg: int = 10, alpha0: float = 1.0, alpha_q: float = 0.5, alpha_min: float = 0.0,
                 G: int = 0, sob_a: float = 880.0, sob_l: float = 16.0, flags: int = 0,
-                col_tile: int = 0) -> Params:
+                col_tile: int = 0, cg_passes: int = 0) -> Params:
     p = Params()
     _check(load().nlinv_params_default(ctypes.byref(p)))
     p.N, p.G, p.J, p.K, p.S_r, p.U, p.batch = N, G, J, K, S_r, U, batch
     p.newton, p.cg, p.flags = newton, cg, flags
     p.alpha0, p.alpha_q, p.alpha_min, p.sob_a, p.sob_l = alpha0, alpha_q, alpha_min, sob_a, sob_l
     p.col_tile = col_tile
+    p.cg_passes = cg_passes
     return p
 
 
 def workspace_size(p: Params) -> int:
     n = ctypes.c_size_t(0)
     _check(load().nlinv_workspace_size(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def set_budget(device: int, budget_bytes: int) -> None:
+    """Cap the summed plan workspaces on HIP device `device` (0 = no cap);
+    plan creation beyond it raises NlinvError with code E_BUDGET."""
+    _check(load().nlinv_set_budget(int(device), int(budget_bytes)))
+
+
+def budget_used(device: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().nlinv_budget_used(int(device), ctypes.byref(n)))
     return n.value
 
 
@@ -150,13 +166,14 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device() if dev.index is None else dev.index)
         nbytes = workspace_size(self.params)
         self.ws_bytes = nbytes
+        self.handle = None
         with torch.cuda.device(self.device):    # the library creates the plan on the current device
+            self._stream = torch.cuda.current_stream(self.device).cuda_stream
+            h = _P()
             raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             off = (-raw.data_ptr()) % 256
             self._raw = raw
             self.ws = raw[off:off + nbytes]
-            self._stream = torch.cuda.current_stream(self.device).cuda_stream
-            h = _P()
             _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
                                               _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
         self.handle = h

@@ -54,6 +54,7 @@ def test_workspace_grows_with_batch(lib):
     (dict(N=64, J=8, K=13, U=0), nl.E_ARG),
     (dict(N=64, J=8, K=13, cg=0), nl.E_ARG),
     (dict(N=64, J=8, K=13, flags=8), nl.E_ARG),   # unknown flag bit
+    (dict(N=64, J=8, K=13, flags=1), nl.E_ARG),   # bit 1 is not a flag
     (dict(N=64, J=8, K=13, alpha0=0.0), nl.E_ARG),
     (dict(N=64, J=8, K=13, alpha_q=1.5), nl.E_ARG),
     (dict(N=64, J=8, K=13, alpha_min=-1.0), nl.E_ARG),
@@ -93,3 +94,4 @@ def test_null_plan_rejected(lib):
     assert lib.nlinv_psf_samples(None, None, 1, 0) == nl.E_ARG
     assert lib.nlinv_get_batch(None) == 0
     assert b"NULL" in lib.nlinv_last_error(None)
+

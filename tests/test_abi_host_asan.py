@@ -65,6 +65,17 @@ int main(void) {
   bad += expect(nlinv_psf_samples(NULL, NULL, 1, 0), NLINV_E_ARG, "psf_samples(NULL)");
   bad += expect(nlinv_psf_spokes(NULL, NULL, 1, 0), NLINV_E_ARG, "psf_spokes(NULL)");
   bad += expect(nlinv_plan_destroy(NULL), NLINV_E_ARG, "destroy(NULL)");
+  /* budget bookkeeping (host-only) */
+  size_t used = 1;
+  bad += expect(nlinv_set_budget(-1, 0), NLINV_E_ARG, "set_budget(-1)");
+  bad += expect(nlinv_set_budget(64, 0), NLINV_E_ARG, "set_budget(64)");
+  bad += expect(nlinv_budget_used(0, NULL), NLINV_E_ARG, "budget_used(NULL)");
+  bad += expect(nlinv_budget_used(0, &used), NLINV_OK, "budget_used");
+  bad += expect(used == 0, 1, "no plans, nothing used");
+  bad += expect(nlinv_set_budget(0, 1 << 20), NLINV_OK, "set_budget");
+  bad += expect(nlinv_set_budget(0, 0), NLINV_OK, "clear budget");
+  nlinv_params_default(&p); p.N = 256; p.J = 64; p.K = 21; p.U = 8; p.batch = 4;
+  bad += expect(nlinv_plan_workspace_size(&p, &ws), NLINV_OK, "plan_workspace_size");
   printf("checks done, %d failed\n", bad);
   return bad != 0;
 }

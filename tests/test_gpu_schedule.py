@@ -27,7 +27,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("N,J,K,B,G,flags", [(64, 8, 13, 3, 0, 0), (160, 10, 15, 1, 0, 0), (120, 3, 9, 2, 480, 0),
-                                             (64, 8, 13, 2, 0, 1)])    # float32 half-transformed grid
+                                             (64, 8, 13, 2, 0, 2)])    # exact gridding
 def test_column_tiles_agree_bit_for_bit(torch, N, J, K, B, G, flags):
     from paper_1701_08361_amd import nlinv as nl
     print(f"[case] column tiles N={N} J={J} K={K} B={B} G={G} flags={flags}", flush=True)
@@ -81,3 +81,38 @@ def test_psf_of_all_samples_equals_psf(torch):
         plan.close()
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("N,J,K,B,seed", [(64, 8, 13, 3, 40), (128, 5, 11, 2, 44), (32, 3, 5, 1, 46)])
+def test_cg_forms_match_oracle(torch, N, J, K, B, seed):
+    """The four-pass CG iteration (direction update, W^-1 p and the vector step
+    folded into the operator's passes, Re<p, q> from the spectrum) and the
+    six-pass one: each item within 1e-3 of the oracle, and the two forms within
+    1e-4 of each other (the same CG up to rounding).  Four-pass results do not
+    depend on the tile schedule (bit for bit)."""
+    from paper_1701_08361_amd import nlinv as nl
+    M, C = 4, 8
+    print(f"[case] cg forms N={N} J={J} K={K} B={B} M={M} C={C}", flush=True)
+    s = [synth.single_frame(seed=seed + b, N=N, J=J, K=K) for b in range(B)]
+    traj = torch.from_numpy(np.concatenate([f.traj for f in s])).cuda()
+    y = torch.from_numpy(np.concatenate([f.y for f in s])).cuda()
+    imgs = {}
+    for passes, tile in ((6, 0), (4, 0), (4, 4)):
+        plan = nl.Plan(N, J, K, batch=B, newton=M, cg=C, cg_passes=passes, col_tile=tile)
+        plan.psf(traj[0].contiguous(), 0)
+        z = plan.grid(traj, y)
+        _, img, _ = plan.reconstruct(z, [0] * B, want_img=True)
+        torch.cuda.synchronize()
+        imgs[(passes, tile)] = img.cpu().numpy()
+        plan.close()
+    assert np.array_equal(imgs[(4, 0)], imgs[(4, 4)])
+    g = O.Geometry.make(N, J)
+    P = O.psf_kernel(s[0].traj[0], g.R, g.G)
+    for b in range(B):
+        assert np.array_equal(s[b].traj, s[0].traj)      # one trajectory (turn 0) for every item
+        xr = O.reconstruct(g, O.grid(s[b].y[0], s[0].traj[0], g.R), P, newton=M, cg_iters=C)
+        ref = O.image(g, xr)
+        e6, e4 = rel(imgs[(6, 0)][b], ref), rel(imgs[(4, 0)][b], ref)
+        d = rel(imgs[(4, 0)][b], imgs[(6, 0)][b])
+        print(f"item {b}: six-pass rel {e6:.2e}, four-pass rel {e4:.2e}, between forms {d:.2e}")
+        assert e6 < 1e-3 and e4 < 1e-3 and d < 1e-4

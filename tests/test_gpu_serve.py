@@ -75,3 +75,31 @@ def test_server_admission_budget(torch):
     srv.release("a")
     srv.admit("b", N, J, Jp, K, U, tr, calib)
     assert srv.used == need
+
+
+def test_library_budget_admission(torch):
+    """nlinv_set_budget: plan creation beyond the device's workspace budget
+    fails with NLINV_E_BUDGET; destroying a plan returns its share."""
+    import gc
+    from paper_1701_08361_amd import nlinv
+    print("[case] library budget admission", flush=True)
+    gc.collect()
+    dev = torch.cuda.current_device()
+    need = nlinv.workspace_size(nlinv.make_params(32, 4, 5))
+    base = nlinv.budget_used(dev)
+    nlinv.set_budget(dev, base + 2 * need)
+    try:
+        a = nlinv.Plan(32, 4, 5)
+        b = nlinv.Plan(32, 4, 5)
+        assert nlinv.budget_used(dev) == base + 2 * need
+        with pytest.raises(nlinv.NlinvError) as ei:
+            nlinv.Plan(32, 4, 5)
+        assert ei.value.code == nlinv.E_BUDGET
+        a.close()
+        assert nlinv.budget_used(dev) == base + need
+        c = nlinv.Plan(32, 4, 5)
+        c.close()
+        b.close()
+        assert nlinv.budget_used(dev) == base
+    finally:
+        nlinv.set_budget(dev, 0)
