@@ -140,8 +140,8 @@ int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace,
 int nlinv_plan_destroy(nlinv_plan plan);
 
 /* Admission by device-memory budget (Sec. 3.1: several slices of a real-time
- * pipeline share one GPU).  With budget_bytes > 0, nlinv_plan_create on HIP
- * device `device` (0..63) fails with
+ * pipeline share one GPU).  With budget_bytes > 0, nlinv_plan_create and
+ * nlinv_plan_create_static on HIP device `device` (0..63) fail with
  * NLINV_E_BUDGET, before touching the device, when the new plan's workspace
  * (nlinv_workspace_size) plus the workspaces of the live plans on that device
  * would exceed budget_bytes; nlinv_plan_destroy returns a plan's share.
@@ -150,6 +150,26 @@ int nlinv_plan_destroy(nlinv_plan plan);
  * summed workspace bytes of the live plans on `device`.  Thread-safe; host-only. */
 int nlinv_set_budget(int32_t device, size_t budget_bytes);
 int nlinv_budget_used(int32_t device, size_t* used_bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): a plan
+ * exactly like nlinv_plan_create's, whose workspace is the library's static
+ * device array of NLINV_STATIC_WORKSPACE_BYTES (128 MiB) instead of a
+ * caller buffer.  Each GPU the library runs on holds its own array until the
+ * process ends; it is set up on the first call on a device (that device
+ * current).  The call allocates no device memory.
+ *   - NLINV_E_WORKSPACE: the parameters need more workspace than the array
+ *     holds (nlinv_workspace_size > NLINV_STATIC_WORKSPACE_BYTES; e.g. 160 px,
+ *     10 coils, 5 turns, batch 1 needs 73 MiB and fits).
+ *   - NLINV_E_STATE: another plan on the static workspace of the current
+ *     device is still alive (one at a time per GPU; destroy it first).
+ * The array keeps the last plan's contents; a new plan rebuilds every table
+ * and PSF kernel it uses.  Plans on it launch eagerly: nlinv_set_graphs(1)
+ * and nlinv_timer_enable return NLINV_E_STATE.  As for every plan, calls
+ * that overlap in time on one plan race; since all static plans of a GPU
+ * share one array, so would two of them, which is why only one may live. */
+#define NLINV_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+int nlinv_plan_create_static(const nlinv_params* p, void* stream, nlinv_plan* out);
 int nlinv_set_stream(nlinv_plan plan, void* stream);
 
 /* PSF kernel of one turn (Sec. 2.2 footnote; Fig. flow: convolution with the

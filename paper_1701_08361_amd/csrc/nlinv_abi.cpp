@@ -50,17 +50,20 @@ struct nlinv_plan_s {
   std::vector<int2> kbn_host;   // per turn: grid points with short / long gridding rows
   int device = 0;               // HIP device the plan was created on
   size_t ws_need = 0;           // its workspace size (counted against the device's budget)
+  bool is_static = false;       // workspace = the device's static array (nlinv_plan_create_static)
 };
 
 namespace {
 
 thread_local std::string g_err;   // errors not tied to a plan
 
-// Per-device admission budget of plan workspaces (nlinv_set_budget).
+// Per-device admission budget of plan workspaces (nlinv_set_budget) and the
+// owner of each device's static workspace (nlinv_plan_create_static).
 constexpr int MAX_DEV = 64;
 std::mutex g_dev_mu;
 size_t g_budget[MAX_DEV] = {};       // 0: no cap
 size_t g_used[MAX_DEV] = {};         // summed workspace sizes of the live plans
+nlinv_plan g_static_owner[MAX_DEV] = {};
 
 int fail(nlinv_plan plan, int code, const std::string& msg) {
   if (plan) plan->err = msg; else g_err = msg;
@@ -457,17 +460,45 @@ int nlinv_sizes(const nlinv_params* p, int32_t* R, int32_t* G, int32_t* Gc, int6
   return NLINV_OK;
 }
 
-// Returns a plan's budget share and frees it.
+// The static workspace of nlinv_plan_create_static: one array per GPU, held
+// by the process until it ends.  In host code `scratch` names a host-side
+// stand-in, never the device array: its device address is looked up once per
+// device (hipGetSymbolAddress, that device current) and only that address is
+// used.
+static __device__ __align__(256) unsigned char scratch[NLINV_STATIC_WORKSPACE_BYTES];
+static void* g_scratch_ptr[MAX_DEV] = {};
+
+// Device address of the current device's static workspace.
+static int static_workspace(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEV) return fail(nullptr, NLINV_E_ARG, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(nullptr, e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+      return fail(nullptr, NLINV_E_HIP, "static workspace has no 256-byte aligned device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NLINV_OK;
+}
+
+// Returns a plan's budget share (and the static workspace) and frees it.
 static void release_plan(nlinv_plan plan) {
   {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     g_used[plan->device] -= std::min(g_used[plan->device], plan->ws_need);
+    if (plan->is_static && g_static_owner[plan->device] == plan) g_static_owner[plan->device] = nullptr;
   }
   delete plan;
 }
 
 static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
-                       nlinv_plan* out) {
+                       nlinv_plan* out, bool is_static) {
   if (!out) return fail(nullptr, NLINV_E_ARG, "out is NULL");
   *out = nullptr;
   Shape s;
@@ -500,10 +531,16 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
                   "device budget exceeded: " + std::to_string(g_used[dev]) + " of " +
                       std::to_string(g_budget[dev]) + " bytes in use, the plan needs " + std::to_string(L.total));
     }
+    if (is_static && g_static_owner[dev] != nullptr) {
+      delete plan;
+      return fail(nullptr, NLINV_E_STATE, "the device's static workspace is held by a live plan (destroy it first)");
+    }
     g_used[dev] += L.total;
+    if (is_static) g_static_owner[dev] = plan;
   }
   plan->device = dev;
   plan->ws_need = L.total;
+  plan->is_static = is_static;
   plan->p = *p;
   plan->s = s;
   plan->stream = reinterpret_cast<hipStream_t>(stream);
@@ -588,7 +625,7 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
 
 int nlinv_plan_create(const nlinv_params* p, void* stream, void* d_workspace, size_t ws_bytes,
                       nlinv_plan* out) {
-  return create_plan(p, stream, d_workspace, ws_bytes, out);
+  return create_plan(p, stream, d_workspace, ws_bytes, out, false);
 }
 
 int nlinv_plan_workspace_size(const nlinv_params* p, size_t* bytes) { return nlinv_workspace_size(p, bytes); }
@@ -606,6 +643,24 @@ int nlinv_budget_used(int32_t device, size_t* used_bytes) {
   std::lock_guard<std::mutex> lk(g_dev_mu);
   *used_bytes = g_used[device];
   return NLINV_OK;
+}
+
+int nlinv_plan_create_static(const nlinv_params* p, void* stream, nlinv_plan* out) {
+  if (!out) return fail(nullptr, NLINV_E_ARG, "out is NULL");
+  *out = nullptr;
+  Shape s;
+  Layout L;
+  std::string err;
+  const int rc = derive(p, &s, &L, &err);
+  if (rc != NLINV_OK) return fail(nullptr, rc, err);
+  if (L.total > NLINV_STATIC_WORKSPACE_BYTES)
+    return fail(nullptr, NLINV_E_WORKSPACE,
+                "the plan needs " + std::to_string(L.total) + " bytes of workspace, more than the static workspace's " +
+                    std::to_string((size_t)NLINV_STATIC_WORKSPACE_BYTES) + " (use nlinv_plan_create)");
+  void* base = nullptr;
+  const int rc2 = static_workspace(&base);
+  if (rc2 != NLINV_OK) return rc2;
+  return create_plan(p, stream, base, NLINV_STATIC_WORKSPACE_BYTES, out, true);
 }
 
 int nlinv_plan_destroy(nlinv_plan plan) {
@@ -1105,12 +1160,16 @@ const char* nlinv_last_error(nlinv_plan plan) {
 
 int nlinv_set_graphs(nlinv_plan plan, int32_t enable) {
   NLV_CHECK(check_plan(plan));
+  if (enable && plan->is_static)
+    return fail(plan, NLINV_E_STATE, "plans on the static workspace launch eagerly (a graph would allocate)");
   plan->graphs = enable != 0;
   return NLINV_OK;
 }
 
 int nlinv_timer_enable(nlinv_plan plan, int32_t kernel_id) {
   NLV_CHECK(check_plan(plan));
+  if (kernel_id != NLINV_KT_NONE && plan->is_static)
+    return fail(plan, NLINV_E_STATE, "plans on the static workspace do not time kernels (events would allocate)");
   if (kernel_id < NLINV_KT_NONE || kernel_id > NLINV_KT_GRID) return fail(plan, NLINV_E_ARG, "unknown kernel id");
   plan->timer_kid = kernel_id;
   plan->ev_used = 0;

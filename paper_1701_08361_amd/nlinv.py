@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libnlinv.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "nlinv.h")
 
 OK, E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_STATE, E_NONFINITE, E_BUDGET = 0, -1, -2, -3, -4, -5, -6, -7
+STATIC_WORKSPACE_BYTES = 128 << 20   # NLINV_STATIC_WORKSPACE_BYTES
 F_EXACT_GRID, F_CHECK_FINITE = 2, 4
 KT = {"none": 0, "toeplitz_rows": 1, "coil_cols": 2, "back_cols": 3, "cg_update": 4,
       "coil_rows": 5, "coilh_rows": 6, "grid": 7}
@@ -56,6 +57,7 @@ def load() -> ctypes.CDLL:
         "nlinv_sizes": [ctypes.POINTER(Params), _P, _P, _P, _P, _P],
         "nlinv_plan_workspace_size": [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
         "nlinv_plan_create": [ctypes.POINTER(Params), _P, _P, ctypes.c_size_t, ctypes.POINTER(_P)],
+        "nlinv_plan_create_static": [ctypes.POINTER(Params), _P, ctypes.POINTER(_P)],
         "nlinv_set_budget": [_I, ctypes.c_size_t],
         "nlinv_budget_used": [_I, ctypes.POINTER(ctypes.c_size_t)],
         "nlinv_plan_destroy": [_P],
@@ -147,7 +149,10 @@ def sizes(p: Params) -> dict:
 class Plan:
     """One NLINV plan: sizes, FP64 tables and a device workspace (a torch tensor)."""
 
-    def __init__(self, N: int, J: int, K: int, device="cuda", **kw):
+    def __init__(self, N: int, J: int, K: int, device="cuda", static_workspace: bool = False, **kw):
+        """static_workspace: take the library's static device array as the
+        workspace (nlinv_plan_create_static: no device allocation; one such
+        plan per GPU at a time) instead of a torch buffer."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -170,12 +175,17 @@ class Plan:
         with torch.cuda.device(self.device):    # the library creates the plan on the current device
             self._stream = torch.cuda.current_stream(self.device).cuda_stream
             h = _P()
-            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-            off = (-raw.data_ptr()) % 256
-            self._raw = raw
-            self.ws = raw[off:off + nbytes]
-            _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
-                                              _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
+            if static_workspace:
+                self._raw = self.ws = None
+                _check(self.lib.nlinv_plan_create_static(ctypes.byref(self.params), _P(self._stream),
+                                                         ctypes.byref(h)))
+            else:
+                raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+                off = (-raw.data_ptr()) % 256
+                self._raw = raw
+                self.ws = raw[off:off + nbytes]
+                _check(self.lib.nlinv_plan_create(ctypes.byref(self.params), _P(self._stream),
+                                                  _P(self.ws.data_ptr()), nbytes, ctypes.byref(h)))
         self.handle = h
 
     # -- helpers ---------------------------------------------------------

@@ -95,3 +95,13 @@ def test_null_plan_rejected(lib):
     assert lib.nlinv_get_batch(None) == 0
     assert b"NULL" in lib.nlinv_last_error(None)
 
+
+def test_static_plan_rejects_oversized_parameters(lib):
+    """nlinv_plan_create_static checks the workspace size against the static
+    array before any device call."""
+    p = nl.make_params(256, 64, 21, U=8, batch=4)
+    assert nl.workspace_size(p) > nl.STATIC_WORKSPACE_BYTES
+    h = ctypes.c_void_p()
+    assert lib.nlinv_plan_create_static(ctypes.byref(p), None, ctypes.byref(h)) == nl.E_WORKSPACE
+    assert not h.value and b"static workspace" in lib.nlinv_last_error(None)
+    assert lib.nlinv_plan_create_static(ctypes.byref(p), None, None) == nl.E_ARG

@@ -74,8 +74,14 @@ int main(void) {
   bad += expect(used == 0, 1, "no plans, nothing used");
   bad += expect(nlinv_set_budget(0, 1 << 20), NLINV_OK, "set_budget");
   bad += expect(nlinv_set_budget(0, 0), NLINV_OK, "clear budget");
+  /* the static workspace refuses parameters that need more than it holds */
   nlinv_params_default(&p); p.N = 256; p.J = 64; p.K = 21; p.U = 8; p.batch = 4;
   bad += expect(nlinv_plan_workspace_size(&p, &ws), NLINV_OK, "plan_workspace_size");
+  bad += expect(ws > NLINV_STATIC_WORKSPACE_BYTES, 1, "oversized for the static workspace");
+  plan = NULL;
+  bad += expect(nlinv_plan_create_static(&p, NULL, &plan), NLINV_E_WORKSPACE, "create_static oversized");
+  bad += expect(plan == NULL, 1, "no static plan on failure");
+  bad += expect(nlinv_plan_create_static(&p, NULL, NULL), NLINV_E_ARG, "create_static(NULL out)");
   printf("checks done, %d failed\n", bad);
   return bad != 0;
 }
