@@ -839,7 +839,9 @@ def main():
                          "cg_state": "f64 vectors (h, r, p, q), f64 dot products and scalars, f64 Newton update"}}
     img_strict = None
     if plain_data is not None:
-        img_strict = torch.zeros(max(args.warmup, 2 * U) + args.steps, N, N, dtype=torch.float32, device="cuda")
+        # frames 0 .. nwarm + steps - 1 of the strict series (run_mode's warm-up count)
+        img_strict = torch.zeros((max(args.warmup, 2 * U) if args.graphs else args.warmup) + args.steps, N, N,
+                                 dtype=torch.float32, device="cuda")
         per, total, kt = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, KT_CLASSES, args.kt_frames,
                                   args.graphs, img_store=img_strict, flags=flags, cg_passes=args.cg_passes_plain)
         fps = args.steps / (total / 1e3)
@@ -847,7 +849,7 @@ def main():
                     "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)},
                     "effective_gbs": 1 * M * (C + 2) * compulsory_bytes_per_cg() / (total / args.steps / 1e3) / 1e9})
         kt_by_batch[1] = kt
-    if plain_data is not None and args.relaxed_o > 0 and True:
+    if plain_data is not None and args.relaxed_o > 0:
         l, o = args.relaxed_l, args.relaxed_o
         img_rel = torch.zeros_like(img_strict)
         nfr, total, per_g, n_end = run_relaxed(torch, nl, plain_data, args.steps, args.warmup, l, o,
@@ -881,7 +883,7 @@ def main():
                                    cg_passes=args.cg_passes_batched)
         kt_by_batch[hb] = kt
         out["hbm_check"] = {"batch": hb, "fps": hb * 2 / (total_hb / 1e3)}
-    if batch_data is not None and args.serve_slices > 0 and True:
+    if batch_data is not None and args.serve_slices > 0:
         S = min(args.serve_slices, len(batch_data))
         serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods}
         for policy in ("plain", "batched"):
@@ -890,7 +892,7 @@ def main():
             serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
-    if plain_data is not None and args.diff_steps > 0 and True:
+    if plain_data is not None and args.diff_steps > 0:
         fwd, tot, grads = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
         out["differentiation"] = {
             "form": "unrolled IRGNM, 5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
@@ -908,10 +910,10 @@ def main():
             pipe[name] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                           "fps": len(lat) / (wall / 1e3)}
         out["serving_pipeline"] = pipe
-    if plain_data is not None and args.autotune_frames and True:
+    if plain_data is not None and args.autotune_frames:
         out["autotune"] = run_autotune(torch, nl, plain_data, [int(f) for f in args.autotune_frames.split(",")],
                                        args.graphs)
-    if args.grid_lut_reps > 0 and True:
+    if args.grid_lut_reps > 0:
         out["grid_choice"] = run_grid_choice(torch, nl, args.grid_lut_reps)
     if mixed_data is not None:
         nfr = sum(len(g[3]) for g in mixed_data)
