@@ -452,12 +452,20 @@ def run_diff(torch, nl, data, steps, newton, cg):
     Returns (forward ms, forward + backward ms) per step and the gradients."""
     from paper_1701_08361_amd import autograd as AG
     from paper_1701_08361_amd import unrolled as UR
-    plan = nl.Plan(N, J, K, U=U)
+    plan = nl.Plan(N, J, K, U=U, newton=newton, cg=cg)
     traj = torch.from_numpy(data[0][0][0:1]).cuda()
     y0 = torch.from_numpy(data[0][1][0:1]).cuda()
     target = torch.from_numpy(data[0][3]).cuda().float()
-    fwd, tot = [], []
+    plan.psf(traj[0], 0)
+    fwd, tot, plain = [], [], []
     grads = {}
+    for i in range(steps + 1):          # the plain solver on the same frame, same counts
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.reconstruct(plan.grid(traj, y0), [0])
+        torch.cuda.synchronize()
+        if i > 0:
+            plain.append((time.perf_counter() - t0) * 1e3)
     for i in range(steps + 1):
         y = y0.clone().requires_grad_(True)
         a0 = torch.tensor(1.0, device="cuda", requires_grad=True)
@@ -466,7 +474,7 @@ def run_diff(torch, nl, data, steps, newton, cg):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m = AG.Reweighted(plan, plan.G, plan.Gc, plan.R, J, sa, sl)
-        x = UR.reconstruct(m, traj, y, N, newton=newton, cg_iters=cg, alpha0=a0)
+        x = UR.reconstruct(m, traj, y, N, newton=newton, cg_iters=cg, alpha0=a0, turns=[0])
         loss = ((UR.image(m, x, N)[0] - target) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -479,7 +487,7 @@ def run_diff(torch, nl, data, steps, newton, cg):
         grads = {"grad_norm_data": float(y.grad.abs().pow(2).sum().sqrt()), "grad_alpha0": float(a0.grad),
                  "grad_sobolev_a": float(sa.grad), "grad_sobolev_l": float(sl.grad)}
     plan.close()
-    return fwd, tot, grads
+    return fwd, tot, plain, grads
 
 
 def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
@@ -893,12 +901,15 @@ def main():
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
     if plain_data is not None and args.diff_steps > 0:
-        fwd, tot, grads = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
+        fwd, tot, plain, grads = run_diff(torch, nl, plain_data, args.diff_steps, 5, C)
         out["differentiation"] = {
-            "form": "unrolled IRGNM, 5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
+            "form": "unrolled IRGNM in the Toeplitz form (gridded data, PSF convolution, hand-written backward), "
+                    "5 Newton x 20 CG, checkpointed per Newton step, batch 1, 160 px 10 coils; "
                     "loss ||image - phantom||^2; gradients w.r.t. the data, alpha_0 and the Sobolev weight's "
-                    "a and l (w = (1 + a|k|^2)^l at 880, 16)",
-            "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50), **grads}
+                    "a and l (w = (1 + a|k|^2)^l at 880, 16); plain = gridding + the library's solver on the "
+                    "same frame with the same counts",
+            "forward_ms": pct(fwd, 50), "forward_backward_ms": pct(tot, 50), "plain_forward_ms": pct(plain, 50),
+            "forward_over_plain": pct(fwd, 50) / pct(plain, 50), **grads}
     if raw_data is not None:
         pipe = {"slices": [{"N": n, "J": j, "J_phys": jp, "K": k} for (n, j, jp, k) in SLICES],
                 "fps_per_slice": args.serve_fps, "periods": args.pipeline_periods,

@@ -16,7 +16,7 @@
  *    grid oversampling; 2N unless given), R = G/2 reconstructed side,
  *    G_c = G/4 coil-spectrum side (Sec. 3.2, coil cropping),
  *    S = K * S_r samples per channel, X = R*R + J*G_c*G_c unknowns.
- *    Supported grids: G in {64, 128, 256, 320, 384, 448, 480, 512} with
+ *    Supported grids: G in {64, 128, 256, 320, 384, 432, 448, 480, 512} with
  *    2N <= G <= 4N.
  *    Every array is on the R x R field of view; for gamma > 1 the N x N
  *    output image is its centre, rows and columns R/2 - floor(N/2) to
@@ -178,8 +178,9 @@ int nlinv_set_stream(nlinv_plan plan, void* stream);
  * P = unnormalised 2D DFT of psf on the G-grid; P is real and is cached in the
  * workspace under `turn` (0 <= turn < U).  d_traj: [K][S_r][2]. */
 int nlinv_psf(nlinv_plan plan, const float* d_traj, int32_t turn);
-/* (also builds the turn's gridding table; copies d_traj to the host and
- * blocks until the table is in the workspace) */
+/* (also builds the turn's gridding table: kernels enqueued on the plan's
+ * stream, which read d_traj there; the call does not wait for the device.
+ * d_traj must stay valid until that work has run.) */
 
 /* The same for a turn acquired with fewer spokes than the plan's K: only the
  * first `spokes` spokes of d_traj [K][S_r][2] count (1 <= spokes <= K,
@@ -208,7 +209,7 @@ int nlinv_psf_samples(nlinv_plan plan, const float* d_traj, int64_t samples, int
  * h_turn == NULL: the exact sum over the samples of d_traj[b].
  * h_turn != NULL (host [B]): item b is sampled on the trajectory of turn
  * h_turn[b].  The PSF kernel and the gridding table of every turn not yet
- * cached are computed from d_traj[b] (as nlinv_psf; this blocks the host).
+ * cached are computed from d_traj[b] (as nlinv_psf, enqueued on the stream).
  * Unless the plan has NLINV_F_EXACT_GRID, z is then formed by Kaiser-Bessel
  * gridding (width 9, oversampling G/R = 2; Beatty et al. 2005): gather onto
  * the G x G grid, inverse 2D FFT, crop, deapodise; relative error ~1e-8
@@ -278,6 +279,48 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
  * turn h_turn[b].  d_xhat, d_p, d_q: [B][X]. */
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
                        double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
+
+/* The pieces of the IRGNM (Sec. 2.2) in the PSF-convolution form, for the
+ * differentiable unrolled reconstruction.  E_x is the image-space part of the
+ * derivative, DF_x = F E_x with E_x(p)_j = c_j d_rho + rho W^-1 d_c_hat_j
+ * (c_j = W^-1 c_hat_j, rho of the linearisation point x), and T = F^H F the
+ * PSF convolution of each item's turn.  Vectors in the unknowns' space are
+ * complex128 ([B][X], interleaved double re, im); linearisation points x are
+ * complex64 as everywhere; images [B][J][R][R] complex64.
+ *   nlinv_apply_normal2: q = E_xa^H T E_xb p + alpha p (= DF_xa^H DF_xb p + alpha p;
+ *                        xa = xb gives the CG operator of the normal-operator
+ *                        equation; xa != xb the terms of its derivative in x).
+ *   nlinv_apply_E:       img = E_x p.
+ *   nlinv_apply_EH:      out = E_x^H img = (sum_j conj(c_j) img_j ; W^-H(conj(rho) img_j)).
+ *   nlinv_nudft:         y = F img per channel, the exact non-uniform DFT (the
+ *                        adjoint of the exact gridding nlinv_grid without turns);
+ *                        R <= 256 (NLINV_E_SIZE otherwise). */
+int nlinv_apply_normal2(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xa, const nlinv_c64* d_xb,
+                        double alpha, const double* d_p, double* d_q);
+int nlinv_apply_E(nlinv_plan plan, const nlinv_c64* d_xhat, const double* d_p, nlinv_c64* d_img);
+int nlinv_apply_EH(nlinv_plan plan, const nlinv_c64* d_xhat, const nlinv_c64* d_img, double* d_out);
+int nlinv_nudft(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_img, nlinv_c64* d_y);
+
+/* One IRGNM update (Sec. 2.2, the update equation) with a given alpha and CG
+ * count: d_xhat <- d_xhat + h, h from `cg` CG iterations (1 <= cg <= 100000)
+ * from h = 0 on (DF^H DF + alpha) h = DF^H (y - F_hat(x_hat)) - alpha (x_hat -
+ * x_prev), with the solver's own kernels (the plan's cg_passes form, FP64 CG
+ * vectors and scalars).  d_z [B][J][R][R] gridded data, h_turn host [B] PSF
+ * kernel per item, d_xprev [B][X] or NULL for (rho = 1, c = 0), d_xhat [B][X]
+ * in/out (must not alias d_xprev); alpha finite and >= 0.  A step of
+ * nlinv_reconstruct is this call with alpha_n and the plan's cg.  It serves
+ * the forward pass of the differentiable unrolled reconstruction. */
+int nlinv_newton_step(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_z, const nlinv_c64* d_xprev,
+                      double alpha, int32_t cg, nlinv_c64* d_xhat);
+
+/* Another Sobolev weight for every later call of this plan (Sec. 3.2, Fig.
+ * weight_func: the weight is a choice).  d_winv: device [G_c][G_c] float32
+ * table of 1 / (G w'(kappa)) in the layout of one coil spectrum block of
+ * x_hat (centred kappa, kappa_y major); the plan's own table holds
+ * 1 / (G (1 + sob_a |kappa/G|^2)^sob_l).  The caller owns d_winv and keeps it
+ * valid and unchanged while it is set; NULL restores the plan's own table.
+ * Captured HIP graphs of the plan are dropped when the table changes. */
+int nlinv_set_coil_weights(nlinv_plan plan, const float* d_winv);
 
 /* Channel compression (Sec. 3.1, preprocessing): virtual channels
  * d_y[b][j][s] = sum_p d_cc[j][p] d_yp[b][p][s] of the J_phys receive channels.

@@ -17,10 +17,13 @@ dL = Re<grad, dx>.
 `ops` is any object with apply_F / apply_DF / apply_DFH(traj, xhat, ...),
 coils(xhat, want_img=False) and apply_WH(coils) in the shapes of
 paper_1701_08361_amd.nlinv.Plan (xhat [B][X], data [B][J][S], coil images
-[B][J][R][R]).  Reweighted gives the same operators under another Sobolev
+[B][J][R][R]); the PSF-convolution form below also uses grid, nudft,
+apply_normal2, apply_E and apply_EH.  Reweighted gives the same operators under another Sobolev
 weight, differentiable in its parameters.
 """
 from __future__ import annotations
+
+import math
 
 import torch
 
@@ -88,6 +91,93 @@ def coils(ops, xhat):
     return _Coils.apply(xhat, ops)
 
 
+# ---------------------------------------------------------------------------
+# The PSF-convolution (Toeplitz) form.  With E_x the image-space part of the
+# derivative (DF_x = F E_x, E_x(p)_j = c_j d_rho + rho W^-1 d_c_hat_j) and
+# T = F^H F, the Newton right-hand side is E_x^H (z - T E_x(rho_x, 0)) with
+# z = F^H y, and the CG operator is E_x^H T E_x + alpha.  E_x(p) is
+# symmetric bilinear in (x, p), so for a real loss with upstream gradient g:
+#   z = F^H y              : grad_y = F g
+#   v = E_x^H img          : grad_img = E_x g,  grad_x = E_g^H img
+#   q = E_x^H T E_x p + a p: grad_p = E_x^H T E_x g + a g,
+#                            grad_x = E_g^H T E_x p + E_p^H T E_x g,
+#                            grad_a = Re<p, g>
+# Unknowns-space vectors are complex128; linearisation points are rounded to
+# the operators' precision (`ops.dtype`: complex64 for the library, whose
+# solver stores its iterates so too).
+# ---------------------------------------------------------------------------
+
+def _pt(ops, t):
+    return t.detach().to(getattr(ops, "dtype", torch.complex64)).contiguous()
+
+
+class _Grid(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, ops, traj):
+        ctx.ops, ctx.traj = ops, traj
+        return ops.grid(traj, y.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.ops.nudft(ctx.traj, g.contiguous()), None, None
+
+
+class _EH(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, img, ops):
+        ctx.ops = ops
+        ctx.save_for_backward(x, img)
+        return ops.apply_EH(_pt(ops, x), img.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        x, img = ctx.saved_tensors
+        g = g.contiguous()
+        gx = ctx.ops.apply_EH(_pt(ctx.ops, g), img.contiguous()) if ctx.needs_input_grad[0] else None
+        gimg = ctx.ops.apply_E(_pt(ctx.ops, x), g) if ctx.needs_input_grad[1] else None
+        return gx, gimg, None
+
+
+class _Normal(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, p, alpha, ops, turns):
+        ctx.ops, ctx.turns = ops, turns
+        ctx.save_for_backward(x, p, alpha)
+        xc = _pt(ops, x)
+        return ops.apply_normal2(turns, xc, xc, p.contiguous(), float(alpha))
+
+    @staticmethod
+    def backward(ctx, g):
+        x, p, alpha = ctx.saved_tensors
+        ops, turns = ctx.ops, ctx.turns
+        g = g.contiguous()
+        xc = _pt(ops, x)
+        gx = gp = ga = None
+        if ctx.needs_input_grad[0]:
+            gx = (ops.apply_normal2(turns, _pt(ops, g), xc, p.contiguous(), 0.0)
+                  + ops.apply_normal2(turns, _pt(ops, p), xc, g, 0.0))
+        if ctx.needs_input_grad[1]:
+            gp = ops.apply_normal2(turns, xc, xc, g, float(alpha))
+        if ctx.needs_input_grad[2]:
+            ga = (p.conj() * g).real.sum().to(alpha.dtype)
+        return gx, gp, ga, None, None
+
+
+def grid(ops, traj, y):
+    """z = F^H y [B][J][R][R] (exact sum), differentiable in y."""
+    return _Grid.apply(y, ops, traj)
+
+
+def EH(ops, x, img):
+    """E_x^H img [B][X] complex128, differentiable in x (complex128) and img."""
+    return _EH.apply(x, img, ops)
+
+
+def normal(ops, turns, x, p, alpha):
+    """E_x^H T E_x p + alpha p [B][X] complex128, differentiable in x, p and alpha."""
+    return _Normal.apply(x, p, torch.as_tensor(alpha, dtype=torch.float64, device=p.device), ops, turns)
+
+
 class Reweighted:
     """The operators of the model under another Sobolev weight
     w'(k) = (1 + a |k|^2)^l (Sec. 3.2, Fig. weight_func), differentiable in a
@@ -114,6 +204,16 @@ class Reweighted:
         # w / w' in logarithms: the weights themselves reach 1e23 at the spectrum's corners
         ratio = torch.exp(l_ref * torch.log1p(a_ref * k2) - l * torch.log1p(a * k2))
         self.d = torch.cat([torch.ones(R * R, dtype=torch.float64, device=dev), ratio.reshape(-1).repeat(J)])
+        # the coil-weight table 1 / (G w') of this weight, for solvers that take one (no gradient)
+        with torch.no_grad():
+            self.winv = torch.exp(-math.log(G) - l * torch.log1p(a * k2))
+
+    @classmethod
+    def from_diagonal(cls, ops, R, d):
+        """The model of the diagonal d itself (no weight parameters)."""
+        m = cls.__new__(cls)
+        m.ops, m.X, m.R, m.d, m.winv = ops, ops.X, R, d, None
+        return m
 
     def _scale(self, x):
         return x * self.d.to(device=x.device, dtype=x.real.dtype)
@@ -129,6 +229,13 @@ class Reweighted:
 
     def coils(self, xhat):
         return coils(self.ops, self._scale(xhat))
+
+    def normal(self, turns, x, p, alpha):
+        # N' = D N_{D x} D + alpha (the weight ratio D is real)
+        return self._scale(normal(self.ops, turns, self._scale(x), self._scale(p), 0.0)) + alpha * p
+
+    def EH(self, x, img):
+        return self._scale(EH(self.ops, self._scale(x), img))
 
 
 class Plain:
@@ -148,6 +255,12 @@ class Plain:
 
     def coils(self, xhat):
         return coils(self.ops, xhat)
+
+    def normal(self, turns, x, p, alpha):
+        return normal(self.ops, turns, x, p, alpha)
+
+    def EH(self, x, img):
+        return EH(self.ops, x, img)
 
 
 def model(ops):

@@ -28,7 +28,7 @@ COMMON = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 
-SOURCES = ["nlinv_launch.hip", "nlinv_abi.cpp"] + [f"nlinv_g{g}.hip" for g in (64, 128, 256, 320, 384, 448, 480, 512)]
+SOURCES = ["nlinv_launch.hip", "nlinv_abi.cpp"] + [f"nlinv_g{g}.hip" for g in (64, 128, 256, 320, 384, 432, 448, 480, 512)]
 
 
 def _compile(src: str) -> str:

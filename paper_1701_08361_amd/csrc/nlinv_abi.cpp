@@ -47,10 +47,10 @@ struct nlinv_plan_s {
   hipStream_t cap_stream = nullptr;
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graph_cache;
   float2* xb = nullptr;   // [B][X] source frames of nlinv_reconstruct_frames
-  std::vector<int2> kbn_host;   // per turn: grid points with short / long gridding rows
   int device = 0;               // HIP device the plan was created on
   size_t ws_need = 0;           // its workspace size (counted against the device's budget)
   bool is_static = false;       // workspace = the device's static array (nlinv_plan_create_static)
+  float* dinv_own = nullptr;    // the plan's own coil-weight table (nlinv_set_coil_weights restores it)
 };
 
 namespace {
@@ -84,88 +84,23 @@ int fail_hip(nlinv_plan plan, hipError_t e, const char* what) {
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 bool supported_grid(int G) {
-  return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 448 || G == 480 || G == 512;
+  return G == 64 || G == 128 || G == 256 || G == 320 || G == 384 || G == 432 || G == 448 || G == 480 ||
+         G == 512;
 }
 
-// Kaiser-Bessel gridding kernel (Beatty, Nishimura, Pauly 2005): width W grid
-// cells at oversampling G / R = 2, shape beta = pi sqrt((W/2)^2 (2 - 1/2)^2 - 0.8).
-constexpr int KB_W = 9;
-constexpr int KB_TAPS = KB_W + 1;   // grid points a sample can reach per axis
+using nlv::KB_TAPS;
+using nlv::KB_W;
 
-double bessel_i0(double x) {        // power series sum_k ((x/2)^k / k!)^2
-  const double q = 0.25 * x * x;
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 200; ++k) {
-    term *= q / ((double)k * k);
-    sum += term;
-    if (term < 1e-17 * sum) break;
-  }
-  return sum;
-}
-
-double kb_beta() {
-  const double sigma = 2.0, hw = KB_W / sigma;
-  return M_PI * std::sqrt(hw * hw * (sigma - 0.5) * (sigma - 0.5) - 0.8);
-}
-
-// kernel value at distance d (grid cells), normalised to 1 at d = 0
-double kb_phi(double d, double beta) {
-  const double t = 1.0 - (2.0 * d / KB_W) * (2.0 * d / KB_W);
-  return t < 0.0 ? 0.0 : bessel_i0(beta * std::sqrt(t)) / bessel_i0(beta);
-}
-
-// its continuous Fourier transform at u cycles per grid cell (|pi W u| < beta)
+// Fourier transform of the Kaiser-Bessel kernel at u cycles per grid cell
+// (|pi W u| < beta): the deapodisation.
 double kb_phi_hat(double u, double beta) {
   const double a = std::sqrt(beta * beta - (M_PI * KB_W * u) * (M_PI * KB_W * u));
-  return KB_W * std::sinh(a) / a / bessel_i0(beta);
-}
-
-// Gather table of one trajectory: for every grid point p = uy * G + ux of the
-// G x G grid (DC at 0, periodic), the samples s within half a kernel width on
-// both axes and their weights phi(ux - G kx_s) phi(uy - G ky_s).  Entries of a
-// grid point are in sample order.
-void kb_table(const float* traj, int S, int G, std::vector<int>& rp, std::vector<int2>& ent) {
-  const double beta = kb_beta();
-  struct Tap { int p; float w; };
-  std::vector<Tap> taps;
-  taps.reserve((size_t)S * KB_TAPS * KB_TAPS);
-  std::vector<int> owner;
-  owner.reserve(taps.capacity());
-  for (int s = 0; s < S; ++s) {
-    const double x = (double)G * traj[2 * s], y = (double)G * traj[2 * s + 1];
-    const int ux0 = (int)std::ceil(x - 0.5 * KB_W), uy0 = (int)std::ceil(y - 0.5 * KB_W);
-    double wx[KB_TAPS], wy[KB_TAPS];
-    for (int a = 0; a < KB_TAPS; ++a) {
-      wx[a] = kb_phi(ux0 + a - x, beta);
-      wy[a] = kb_phi(uy0 + a - y, beta);
-    }
-    for (int by = 0; by < KB_TAPS; ++by) {
-      if (wy[by] == 0.0) continue;
-      const int py = ((uy0 + by) % G + G) % G;
-      for (int bx = 0; bx < KB_TAPS; ++bx) {
-        if (wx[bx] == 0.0) continue;
-        const int px = ((ux0 + bx) % G + G) % G;
-        taps.push_back(Tap{py * G + px, (float)(wy[by] * wx[bx])});
-        owner.push_back(s);
-      }
-    }
-  }
-  const size_t GG = (size_t)G * G;
-  rp.assign(GG + 1, 0);
-  for (const Tap& t : taps) ++rp[t.p + 1];
-  for (size_t p = 0; p < GG; ++p) rp[p + 1] += rp[p];
-  std::vector<int> fill(rp.begin(), rp.end() - 1);
-  ent.resize(taps.size());
-  for (size_t k = 0; k < taps.size(); ++k) {
-    int w;
-    std::memcpy(&w, &taps[k].w, 4);
-    ent[fill[taps[k].p]++] = make_int2(owner[k], w);
-  }
+  return KB_W * std::sinh(a) / a / nlv::kb_bessel_i0(beta);
 }
 
 // Validates the parameters, fills the shape and the workspace layout.
 struct Layout {
-  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBC, KG, COV, FLAG,
+  size_t tw, dinv, P, psf, CO, U1, U2, PR, IMG, GS, H, Rv, Pv0, Pv1, Q, pq, rr0, rr1, XB, KBR, KBE, KBP, KBN, KBS, KBQ, KBC, KG, COV, FLAG,
       VR, VP, PDFP, PPP, SCAL,
       total;
 };
@@ -178,7 +113,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   // view R = G/2 holds the N x N image in its centre
   const int G = p->G == 0 ? 2 * p->N : p->G;
   if (G < 2 * p->N || G > 4 * p->N) return bad(NLINV_E_SIZE, "G must be in [2N, 4N] (G = 2 gamma N, 1 <= gamma <= 2)");
-  if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384, 448, 480 or 512");
+  if (!supported_grid(G)) return bad(NLINV_E_SIZE, "unsupported grid: G must be 64, 128, 256, 320, 384, 432, 448, 480 or 512");
   if (p->J < 1 || p->J > 64) return bad(NLINV_E_ARG, "J must be in [1, 64]");
   if (p->K < 1 || (p->K % 2) == 0) return bad(NLINV_E_ARG, "K must be a positive odd number");
   const int S_r = p->S_r == 0 ? 2 * p->N : p->S_r;
@@ -225,7 +160,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   // out (exact gridding only) when they would take more than 2 GiB
   S.kbe_stride = (long long)S.S * KB_TAPS * KB_TAPS;
   const double kb_bytes = (double)S.U * (2.0 * G * G + 3 + 2.0 * S.kbe_stride) * 4.0 +
-                          (double)S.B * S.J * G * G * 8.0;
+                          (double)S.B * S.J * G * G * 8.0 + (double)S.kbe_stride * 8.0 + (double)G * G * 4.0;
   S.kb = (p->flags & NLINV_F_EXACT_GRID) == 0 && kb_bytes <= 2147483648.0;
 
   size_t off = 0;
@@ -266,6 +201,8 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->KBE = take(S.kb ? (size_t)S.U * (size_t)S.kbe_stride * 8 : 0);
   L->KBP = take(S.kb ? (size_t)S.U * Gs * Gs * 4 : 0);
   L->KBN = take(S.kb ? (size_t)S.U * 8 : 0);
+  L->KBS = take(S.kb ? (size_t)S.kbe_stride * 8 : 0);
+  L->KBQ = take(S.kb ? (size_t)Gs * Gs * 4 : 0);
   L->KBC = take(S.kb ? R * 4 : 0);
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
   L->COV = take((size_t)nlv::MAX_JP * nlv::MAX_JP * c16);
@@ -363,42 +300,13 @@ int coils_into(nlinv_plan plan, const float2* xh, float2* co) {
   return NLINV_OK;
 }
 
-// PSF kernel and (if enabled) Kaiser-Bessel gridding table of one turn from
-// its trajectory (device, [K][S_r][2]).  The table is built on the host, so
-// this waits for the trajectory copy and the upload.
-// PSF kernel and gridding table of `turn` from its first S samples (S <= s.S).
+// PSF kernel and (if enabled) Kaiser-Bessel gridding table of `turn` from the
+// first S samples (S <= s.S) of its trajectory (device, [K][S_r][2]); both
+// are built by kernels on the plan's stream, so the call does not wait.
 int build_turn(nlinv_plan plan, const float* d_traj, int turn, int S) {
   const Shape& s = plan->s;
   NLV_HIP(plan, nlv::launch_psf(s, plan->w, plan->stream, d_traj, S, turn));
-  if (s.kb) {
-    std::vector<float> traj((size_t)S * 2);
-    NLV_HIP(plan, hipMemcpyAsync(traj.data(), d_traj, traj.size() * sizeof(float), hipMemcpyDeviceToHost,
-                                 plan->stream));
-    NLV_HIP(plan, hipStreamSynchronize(plan->stream));
-    std::vector<int> rp;
-    std::vector<int2> ent;
-    kb_table(traj.data(), S, s.G, rp, ent);
-    if ((long long)ent.size() > s.kbe_stride) return fail(plan, NLINV_E_SIZE, "gridding table overflow");
-    // grid points by row length: short rows (one thread each) from the front,
-    // long rows (one wavefront each) from the back
-    const int GG = s.G * s.G;
-    std::vector<int> pts(GG);
-    int ns = 0, nl = 0;
-    for (int p = 0; p < GG; ++p) {
-      if (rp[p + 1] - rp[p] <= nlv::KB_SHORT) pts[ns++] = p;
-      else pts[GG - 1 - nl++] = p;
-    }
-    plan->kbn_host[turn] = make_int2(ns, nl);
-    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbp + (size_t)turn * GG, pts.data(), pts.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, plan->stream));
-    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbn + turn, &plan->kbn_host[turn], sizeof(int2), hipMemcpyHostToDevice,
-                                 plan->stream));
-    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbr + (size_t)turn * ((size_t)s.G * s.G + 1), rp.data(),
-                                 rp.size() * sizeof(int), hipMemcpyHostToDevice, plan->stream));
-    NLV_HIP(plan, hipMemcpyAsync(plan->w.kbe + (size_t)turn * s.kbe_stride, ent.data(), ent.size() * sizeof(int2),
-                                 hipMemcpyHostToDevice, plan->stream));
-    NLV_HIP(plan, hipStreamSynchronize(plan->stream));
-  }
+  if (s.kb) NLV_HIP(plan, nlv::launch_kb_table(s, plan->w, plan->stream, d_traj, S, turn));
   plan->psf_valid[turn] = 1;
   return NLINV_OK;
 }
@@ -555,6 +463,7 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
   w.lt = &plan->lt;
   w.tw = reinterpret_cast<double2*>(base + L.tw);
   w.dinv = reinterpret_cast<float*>(base + L.dinv);
+  plan->dinv_own = w.dinv;
   w.P = reinterpret_cast<float*>(base + L.P);
   w.psf = reinterpret_cast<double2*>(base + L.psf);
   w.CO = reinterpret_cast<float2*>(base + L.CO);
@@ -576,8 +485,8 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
   w.kbe = reinterpret_cast<int2*>(base + L.KBE);
   w.kbp = reinterpret_cast<int*>(base + L.KBP);
   w.kbn = reinterpret_cast<int2*>(base + L.KBN);
-  plan->kbn_host.assign(s.U, make_int2(0, 0));
-  w.kbn_host = plan->kbn_host.data();
+  w.kbs = reinterpret_cast<int2*>(base + L.KBS);
+  w.kbq = reinterpret_cast<int*>(base + L.KBQ);
   w.kbc = reinterpret_cast<float*>(base + L.KBC);
   w.KG = reinterpret_cast<float2*>(base + L.KG);
   w.cov = reinterpret_cast<double2*>(base + L.COV);
@@ -604,7 +513,7 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
   }
   // deapodisation of the Kaiser-Bessel gridding, 1 / (sqrt(R) c(r)) per axis
   std::vector<float> kbc(s.R);
-  const double beta = kb_beta();
+  const double beta = nlv::kb_beta();
   for (int i = 0; i < s.R; ++i)
     kbc[i] = (float)(1.0 / (std::sqrt((double)s.R) * kb_phi_hat((double)(i - s.R / 2) / s.G, beta)));
   hipError_t e = hipMemcpyAsync(w.tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, plan->stream);
@@ -739,6 +648,83 @@ static int cg_passes(nlinv_plan plan) { return plan->p.cg_passes == 4 ? 4 : 6; }
 
 // Enqueue Newton steps m0 <= m < m1 of the reconstruction on plan->stream
 // (validated arguments); alpha_m follows the schedule from step 0.
+// Enqueue one IRGNM update x_hat <- x_hat + h on plan->stream: the right-hand
+// side at x_hat, then C CG iterations from h = 0 (validated arguments).
+static int enqueue_newton_step(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z, const float2* xp,
+                               float2* xh, double alpha, int C) {
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  hipStream_t st = plan->stream;
+  const Shape& sg = s;
+  const int kt_toep = NLINV_KT_TOEPLITZ_ROWS;
+  // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
+  NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(sg, w, st, xh); }));
+  NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+            return plan->t->cols_fwd(sg, w, st, 0, w.CO, xh, nullptr, w.U2);
+          }));
+  NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
+  NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
+            return plan->t->cols_back(sg, w, st, 1, w.U2, w.CO, xh, z);
+          }));
+  NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+            return plan->t->coilh_rows(sg, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
+          }));
+  NLV_HIP(plan, nlv::launch_cg_init(s, w, st, xh, xp, alpha));
+
+  int ncur = s.NX3 + s.NCI, nprev = 0;
+  if (cg_passes(plan) == 4) {
+    // four dependent kernels per CG iteration (see the four-pass section of
+    // nlinv_kernels.h): the direction update, the x-stage of W^-1 p and the
+    // CG vector updates ride in the operator's passes
+    for (int i = 0; i < C; ++i) {
+      double2* pn = w.Pv[i & 1];
+      const double2* po = w.Pv[(i + 1) & 1];
+      const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
+      const int first = i == 0, last = i == C - 1;
+      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+                return plan->t->cg_cols_fwd(sg, w, st, xh, po, pn, sc, first);
+              }));
+      NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->cg_toep_rows(sg, w, st, turns); }));
+      const nlv::CGRed red{w.scal, w.pdfp, s.NTB, s.NTB, w.ppp, s.NPP, s.NPP, w.rr[i & 1], ncur, s.stride, alpha, 0};
+      NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] { return plan->t->cg_cols_back(sg, w, st, xh, red); }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+                return plan->t->cg_coilh(sg, w, st, pn, xh, alpha, w.rr[(i + 1) & 1], first, last);
+              }));
+      nprev = ncur;
+      ncur = s.NX3 + s.NRQ;
+    }
+  } else {
+    // six dependent kernels per CG iteration: coil rows with the direction
+    // update, the operator's four passes, the CG vector step
+    for (int i = 0; i < C; ++i) {
+      double2* pc = w.Pv[i & 1];
+      double2* pp = w.Pv[(i + 1) & 1];
+      const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
+      const bool upd = i > 0;
+      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
+                return plan->t->coil_rows_cg(sg, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
+                                             upd ? pc : nullptr, sc);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
+                return plan->t->cols_fwd(sg, w, st, 1, w.CO, xh, pc, w.U2);
+              }));
+      NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
+                return plan->t->cols_back(sg, w, st, 0, w.U2, w.CO, xh, nullptr);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
+                return plan->t->coilh_rows(sg, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
+              }));
+      NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
+                return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh);
+              }));
+      nprev = ncur;
+      ncur = s.NCH;
+    }
+  }
+  return NLINV_OK;
+}
+
 static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, const float2* z,
                                const float2* xp, float2* xh, int init, int m0, int m1, float* d_img,
                                float2* d_coils) {
@@ -752,74 +738,7 @@ static int enqueue_reconstruct(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   double alpha = plan->p.alpha0;
   for (int n = 0; n < m0; ++n) alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
   for (int n = m0; n < m1; ++n) {
-    const Shape& sg = s;
-    const int kt_toep = NLINV_KT_TOEPLITZ_ROWS;
-    // right-hand side: DF^H (y - F x_n) - alpha (x_n - x_prev), in image space through z
-    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] { return plan->t->coil_rows(sg, w, st, xh); }));
-    NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-              return plan->t->cols_fwd(sg, w, st, 0, w.CO, xh, nullptr, w.U2);
-            }));
-    NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
-    NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-              return plan->t->cols_back(sg, w, st, 1, w.U2, w.CO, xh, z);
-            }));
-    NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
-              return plan->t->coilh_rows(sg, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
-            }));
-    NLV_HIP(plan, nlv::launch_cg_init(s, w, st, xh, xp, alpha));
-
-    int ncur = s.NX3 + s.NCI, nprev = 0;
-    const int C = plan->p.cg;
-    if (cg_passes(plan) == 4) {
-      // four dependent kernels per CG iteration (see the four-pass section of
-      // nlinv_kernels.h): the direction update, the x-stage of W^-1 p and the
-      // CG vector updates ride in the operator's passes
-      for (int i = 0; i < C; ++i) {
-        double2* pn = w.Pv[i & 1];
-        const double2* po = w.Pv[(i + 1) & 1];
-        const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
-        const int first = i == 0, last = i == C - 1;
-        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-                  return plan->t->cg_cols_fwd(sg, w, st, xh, po, pn, sc, first);
-                }));
-        NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->cg_toep_rows(sg, w, st, turns); }));
-        const nlv::CGRed red{w.scal, w.pdfp, s.NTB, s.NTB, w.ppp, s.NPP, s.NPP, w.rr[i & 1], ncur, s.stride, alpha, 0};
-        NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] { return plan->t->cg_cols_back(sg, w, st, xh, red); }));
-        NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
-                  return plan->t->cg_coilh(sg, w, st, pn, xh, alpha, w.rr[(i + 1) & 1], first, last);
-                }));
-        nprev = ncur;
-        ncur = s.NX3 + s.NRQ;
-      }
-    } else {
-      // six dependent kernels per CG iteration: coil rows with the direction
-      // update, the operator's four passes, the CG vector step
-      for (int i = 0; i < C; ++i) {
-        double2* pc = w.Pv[i & 1];
-        double2* pp = w.Pv[(i + 1) & 1];
-        const Partials sc{w.rr[i & 1], ncur, w.rr[(i + 1) & 1], nprev, s.stride};
-        const bool upd = i > 0;
-        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_ROWS, [&] {
-                  return plan->t->coil_rows_cg(sg, w, st, upd ? pp : pc, upd ? w.Rv : nullptr,
-                                               upd ? pc : nullptr, sc);
-                }));
-        NLV_HIP(plan, timed(plan, NLINV_KT_COIL_COLS, [&] {
-                  return plan->t->cols_fwd(sg, w, st, 1, w.CO, xh, pc, w.U2);
-                }));
-        NLV_HIP(plan, timed(plan, kt_toep, [&] { return plan->t->toep_rows(sg, w, st, turns); }));
-        NLV_HIP(plan, timed(plan, NLINV_KT_BACK_COLS, [&] {
-                  return plan->t->cols_back(sg, w, st, 0, w.U2, w.CO, xh, nullptr);
-                }));
-        NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
-                  return plan->t->coilh_rows(sg, w, st, 0, pc, xh, nullptr, alpha, w.Q, nullptr);
-                }));
-        NLV_HIP(plan, timed(plan, NLINV_KT_CG_UPDATE, [&] {
-                  return nlv::launch_cg_update(s, w, st, i, i == C - 1, pc, sc, xh);
-                }));
-        nprev = ncur;
-        ncur = s.NCH;
-      }
-    }
+    NLV_CHECK(enqueue_newton_step(plan, turns, z, xp, xh, alpha, plan->p.cg));
     alpha = std::max(alpha * plan->p.alpha_q, plan->p.alpha_min);
   }
 
@@ -905,6 +824,37 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
     NLV_CHECK(body());
   }
   return check_finite(plan, xh, (long long)plan->s.B * plan->s.X);
+}
+
+int nlinv_newton_step(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_z, const nlinv_c64* d_xprev,
+                      double alpha, int32_t cg, nlinv_c64* d_xhat) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_z, "d_z"));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_xprev, "d_xprev", true));
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(plan, NLINV_E_ARG, "alpha must be finite and >= 0");
+  if (cg < 1 || cg > 100000) return fail(plan, NLINV_E_ARG, "cg must be in [1, 100000]");
+  if (d_xprev && (const void*)d_xprev == (const void*)d_xhat)
+    return fail(plan, NLINV_E_ARG, "d_xhat must not alias d_xprev");
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+  NLV_CHECK(enqueue_newton_step(plan, turns, reinterpret_cast<const float2*>(d_z),
+                                reinterpret_cast<const float2*>(d_xprev), reinterpret_cast<float2*>(d_xhat), alpha,
+                                cg));
+  return check_finite(plan, reinterpret_cast<float2*>(d_xhat), (long long)plan->s.B * plan->s.X);
+}
+
+int nlinv_set_coil_weights(nlinv_plan plan, const float* d_winv) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_winv, "d_winv", true));
+  float* t = d_winv ? const_cast<float*>(d_winv) : plan->dinv_own;
+  if (t != plan->w.dinv) {
+    // captured graphs hold the table's address: drop them
+    for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    plan->graph_cache.clear();
+    plan->w.dinv = t;
+  }
+  return NLINV_OK;
 }
 
 // Frames n0 .. n0+count-1 of one series under the relaxed temporal coupling.
@@ -1122,6 +1072,78 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
   NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr));
   NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, pd, xh, nullptr, alpha, w.Q, nullptr));
   NLV_HIP(plan, nlv::launch_finalize(s, w, st, pd, alpha, q));
+  return NLINV_OK;
+}
+
+int nlinv_apply_normal2(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xa, const nlinv_c64* d_xb,
+                        double alpha, const double* d_p, double* d_q) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_xa, "d_xa"));
+  NLV_CHECK(check_ptr(plan, d_xb, "d_xb"));
+  NLV_CHECK(check_ptr(plan, d_p, "d_p"));
+  NLV_CHECK(check_ptr(plan, d_q, "d_q"));
+  if (!std::isfinite(alpha)) return fail(plan, NLINV_E_ARG, "alpha must be finite");
+  if ((const void*)d_p == (const void*)d_q) return fail(plan, NLINV_E_ARG, "d_q must not alias d_p");
+  nlv::TurnArgs turns;
+  NLV_CHECK(turns_of(plan, h_turn, &turns));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  hipStream_t st = plan->stream;
+  const float2* xa = reinterpret_cast<const float2*>(d_xa);
+  const float2* xb = reinterpret_cast<const float2*>(d_xb);
+  const double2* p = reinterpret_cast<const double2*>(d_p);
+  const Partials none{};
+  // coil images of the forward point (cols_fwd) and of the adjoint point (cols_back)
+  NLV_CHECK(coils_into(plan, xb, w.CO));
+  NLV_CHECK(coils_into(plan, xa, w.IMG));
+  NLV_HIP(plan, plan->t->coil_rows_cg(s, w, st, p, nullptr, nullptr, none));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xb, p, w.U2));
+  NLV_HIP(plan, plan->t->toep_rows(s, w, st, turns));
+  NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.IMG, xa, nullptr));
+  NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, p, xa, nullptr, alpha, w.Q, nullptr));
+  NLV_HIP(plan, nlv::launch_finalize(s, w, st, p, alpha, reinterpret_cast<double2*>(d_q)));
+  return NLINV_OK;
+}
+
+int nlinv_apply_E(nlinv_plan plan, const nlinv_c64* d_xhat, const double* d_p, nlinv_c64* d_img) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_p, "d_p"));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  const double2* p = reinterpret_cast<const double2*>(d_p);
+  const Partials none{};
+  NLV_CHECK(coils_into(plan, xh, w.CO));
+  NLV_HIP(plan, plan->t->coil_rows_cg(s, w, plan->stream, p, nullptr, nullptr, none));
+  NLV_HIP(plan, plan->t->cols_fwd(s, w, plan->stream, 3, w.CO, xh, p, d_img));
+  return NLINV_OK;
+}
+
+int nlinv_apply_EH(nlinv_plan plan, const nlinv_c64* d_xhat, const nlinv_c64* d_img, double* d_out) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_xhat, "d_xhat"));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img"));
+  NLV_CHECK(check_ptr(plan, d_out, "d_out"));
+  const Shape& s = plan->s;
+  Bufs& w = plan->w;
+  const float2* xh = reinterpret_cast<const float2*>(d_xhat);
+  NLV_CHECK(coils_into(plan, xh, w.CO));
+  NLV_HIP(plan, plan->t->cols_back(s, w, plan->stream, 2, d_img, w.CO, xh, nullptr));
+  NLV_HIP(plan, plan->t->coilh_rows(s, w, plan->stream, 2, nullptr, xh, nullptr, 0.0, w.Q, nullptr));
+  NLV_HIP(plan, nlv::launch_finalize(s, w, plan->stream, nullptr, 0.0, reinterpret_cast<double2*>(d_out)));
+  return NLINV_OK;
+}
+
+int nlinv_nudft(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_img, nlinv_c64* d_y) {
+  NLV_CHECK(check_plan(plan));
+  NLV_CHECK(check_ptr(plan, d_traj, "d_traj"));
+  NLV_CHECK(check_ptr(plan, d_img, "d_img"));
+  NLV_CHECK(check_ptr(plan, d_y, "d_y"));
+  if (plan->s.R > 256) return fail(plan, NLINV_E_SIZE, "the exact forward transform supports R <= 256");
+  NLV_HIP(plan, nlv::launch_nudft_fwd(plan->s, plan->stream, d_traj, reinterpret_cast<const float2*>(d_img),
+                                      reinterpret_cast<float2*>(d_y)));
   return NLINV_OK;
 }
 

@@ -279,6 +279,7 @@ template <> struct FS<128> { static constexpr int G1 = 16, G2 = 8;  };
 template <> struct FS<256> { static constexpr int G1 = 16, G2 = 16; };
 template <> struct FS<320> { static constexpr int G1 = 16, G2 = 20; };
 template <> struct FS<384> { static constexpr int G1 = 16, G2 = 24; };
+template <> struct FS<432> { static constexpr int G1 = 16, G2 = 27; };
 template <> struct FS<448> { static constexpr int G1 = 16, G2 = 28; };
 template <> struct FS<480> { static constexpr int G1 = 16, G2 = 30; };
 template <> struct FS<512> { static constexpr int G1 = 16, G2 = 32; };

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace nlv {
@@ -16,6 +17,35 @@ constexpr int RHOQ_E = 1;     // rho-block elements per thread of the q_rho bloc
 constexpr int VT = 256;       // threads per block in the vector / NUDFT kernels
 constexpr int MAXB = 64;      // largest batch (turn table passed by value)
 constexpr int KB_SHORT = 16;  // gridding rows up to this length take one thread
+constexpr int KB_LONG_BLOCKS = 256;  // blocks per item of the long-row gridding kernels (grid-stride)
+
+// Kaiser-Bessel gridding kernel (Beatty, Nishimura, Pauly 2005): width W grid
+// cells at oversampling G / R = 2, shape beta = pi sqrt((W/2)^2 (2 - 1/2)^2 - 0.8).
+// The same functions run on the host (deapodisation) and on the device (tables).
+constexpr int KB_W = 9;
+constexpr int KB_TAPS = KB_W + 1;   // grid points a sample can reach per axis
+
+__host__ __device__ inline double kb_bessel_i0(double x) {   // sum_k ((x/2)^k / k!)^2
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+__host__ __device__ inline double kb_beta() {
+  const double sigma = 2.0, hw = KB_W / sigma;
+  return M_PI * sqrt(hw * hw * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+}
+
+// kernel value at distance d (grid cells), normalised to 1 at d = 0
+__host__ __device__ inline double kb_phi(double d, double beta) {
+  const double t = 1.0 - (2.0 * d / KB_W) * (2.0 * d / KB_W);
+  return t < 0.0 ? 0.0 : kb_bessel_i0(beta * sqrt(t)) / kb_bessel_i0(beta);
+}
 
 struct TurnArgs { int32_t t[MAXB]; };
 
@@ -100,8 +130,9 @@ struct Bufs {
   int* kbr;       // [U][G*G+1] gridding table row starts (per grid point)
   int2* kbe;      // [U][kbe_stride] (sample index, weight bits) per table entry
   int* kbp;       // [U][G*G] grid points: short rows from the front, long rows from the back
-  int2* kbn;      // [U] (short, long) point counts (device)
-  const int2* kbn_host;  // the same counts on the host (launch sizes)
+  int2* kbn;      // [U] (short, long) point counts
+  int2* kbs;      // [kbe_stride] staging of one turn's entries while its table is built
+  int* kbq;       // [G*G] per-point fill cursors while a table is built
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
   double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
@@ -185,6 +216,8 @@ hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int i
 // block (image_block false) the image part is alpha p, or zero when p is null
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
                            double alpha, float2* out, bool image_block = true);
+hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
+                           double alpha, double2* out, bool image_block = true);
 hipError_t launch_to_double(const Shape& s, hipStream_t st, double2* dst, const float2* src);
 // mode 1: (rho = 1, c = 0); 2: copy xprev [B][X]; 3: broadcast xprev [X] to every item
 hipError_t launch_init_x(const Shape& s, hipStream_t st, float2* xh, const float2* xprev, int mode);
@@ -195,6 +228,7 @@ hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, c
                             float2* y);
 // PSF kernel of `turn` from the first S samples of traj (S <= s.S)
 hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn);
+hipError_t launch_kb_table(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn);
 // channel compression y [B][J][S] = cc [J][Jp] x yp [B][Jp][S]; covariance of one frame [Jp][S]
 constexpr int MAX_JP = 128;
 hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y);

@@ -1024,38 +1024,40 @@ k_kb_gather_long(const int* __restrict__ rp, const int2* __restrict__ ent, const
                  const float2* __restrict__ y, float2* __restrict__ grid, int J, int S) {
   constexpr int GG = G * G;
   const int b = blockIdx.y, t = turns.t[b];
-  const int q = blockIdx.x * (VT / 64) + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (q >= counts[t].y) return;                       // wave-uniform
-  const int p = pts[(size_t)t * GG + GG - 1 - q];     // long points are stored from the end
+  const int lane = threadIdx.x & 63;
+  const int nl = counts[t].y, nw = gridDim.x * (VT / 64);
   const int* r = rp + t * rp_stride;
   const int2* e = ent + t * ent_stride;
-  const int e0 = r[p], e1 = r[p + 1];
-  for (int j0 = 0; j0 < J; j0 += KBJ) {
-    const int nj = J - j0 < KBJ ? J - j0 : KBJ;
-    double2 acc[KBJ];
+  for (int q = blockIdx.x * (VT / 64) + (int)(threadIdx.x >> 6); q < nl; q += nw) {   // wave-uniform
+    const int p = pts[(size_t)t * GG + GG - 1 - q];     // long points are stored from the end
+    const int e0 = r[p], e1 = r[p + 1];
+    for (int j0 = 0; j0 < J; j0 += KBJ) {
+      const int nj = J - j0 < KBJ ? J - j0 : KBJ;
+      double2 acc[KBJ];
 #pragma unroll
-    for (int c = 0; c < KBJ; ++c) acc[c] = make_double2(0.0, 0.0);
-    const float2* yb = y + ((size_t)b * J + j0) * S;
-    for (int k = e0 + lane; k < e1; k += 64) {
-      const int2 en = e[k];
-      const double wv = (double)__int_as_float(en.y);
+      for (int c = 0; c < KBJ; ++c) acc[c] = make_double2(0.0, 0.0);
+      const float2* yb = y + ((size_t)b * J + j0) * S;
+      for (int k = e0 + lane; k < e1; k += 64) {
+        const int2 en = e[k];
+        const double wv = (double)__int_as_float(en.y);
 #pragma unroll
-      for (int c = 0; c < KBJ; ++c) {
-        if (c < nj) {
-          const float2 v = yb[(size_t)c * S + en.x];
-          acc[c].x += wv * v.x;
-          acc[c].y += wv * v.y;
+        for (int c = 0; c < KBJ; ++c) {
+          if (c < nj) {
+            const float2 v = yb[(size_t)c * S + en.x];
+            acc[c].x += wv * v.x;
+            acc[c].y += wv * v.y;
+          }
         }
       }
-    }
 #pragma unroll
-    for (int c = 0; c < KBJ; ++c) {
-      double ax = acc[c].x, ay = acc[c].y;
-      for (int off = 32; off > 0; off >>= 1) {
-        ax += __shfl_down(ax, off, 64);
-        ay += __shfl_down(ay, off, 64);
+      for (int c = 0; c < KBJ; ++c) {
+        double ax = acc[c].x, ay = acc[c].y;
+        for (int off = 32; off > 0; off >>= 1) {
+          ax += __shfl_down(ax, off, 64);
+          ay += __shfl_down(ay, off, 64);
+        }
+        if (lane == 0 && c < nj) grid[((size_t)b * J + j0 + c) * GG + p] = make_float2((float)ax, (float)ay);
       }
-      if (lane == 0 && c < nj) grid[((size_t)b * J + j0 + c) * GG + p] = make_float2((float)ax, (float)ay);
     }
   }
 }
@@ -1295,27 +1297,17 @@ struct GLaunch {
   static hipError_t kb_grid_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns,
                               const float2* y, float2* z) {
     constexpr int RT = row_lines<G>();
-    // launch sizes cover the largest short / long point counts of the batch's turns
-    int ns = 0, nl = 0;
-    for (int b = 0; b < s.B; ++b) {
-      ns = ns > w.kbn_host[turns.t[b]].x ? ns : w.kbn_host[turns.t[b]].x;
-      nl = nl > w.kbn_host[turns.t[b]].y ? nl : w.kbn_host[turns.t[b]].y;
-    }
+    // the point counts live on the device (the tables are built there): the
+    // short-row launch covers every grid point, the long-row one strides
     const long long rps = (long long)G * G + 1;
-    hipError_t e = hipSuccess;
-    if (ns > 0) {
-      k_kb_gather_short<G><<<dim3((ns + VT - 1) / VT, s.B), VT, 0, st>>>(w.kbr, w.kbe, w.kbp, w.kbn, rps, s.kbe_stride,
-                                                                       turns, y, w.KG, s.J, s.S);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    if (nl > 0) {
-      constexpr int WPB = VT / 64;
-      k_kb_gather_long<G><<<dim3((nl + WPB - 1) / WPB, s.B), VT, 0, st>>>(w.kbr, w.kbe, w.kbp, w.kbn, rps, s.kbe_stride,
-                                                                        turns, y, w.KG, s.J, s.S);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+    k_kb_gather_short<G><<<dim3((G * G + VT - 1) / VT, s.B), VT, 0, st>>>(w.kbr, w.kbe, w.kbp, w.kbn, rps,
+                                                                        s.kbe_stride, turns, y, w.KG, s.J, s.S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_kb_gather_long<G><<<dim3(KB_LONG_BLOCKS, s.B), VT, 0, st>>>(w.kbr, w.kbe, w.kbp, w.kbn, rps, s.kbe_stride,
+                                                                  turns, y, w.KG, s.J, s.S);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int nlines = s.B * s.J * G;
     k_kb_rows<G, S2><<<(nlines + RT - 1) / RT, TH_ROW1, 0, st>>>(w.KG, static_cast<S2*>(w.U2), w.tw, nlines);
     e = hipGetLastError();

@@ -11,6 +11,7 @@ const GTable* table_g128();
 const GTable* table_g256();
 const GTable* table_g320();
 const GTable* table_g384();
+const GTable* table_g432();
 const GTable* table_g448();
 const GTable* table_g480();
 const GTable* table_g512();
@@ -22,6 +23,7 @@ const GTable* table_for(int G) {
     case 256: return table_g256();
     case 320: return table_g320();
     case 384: return table_g384();
+    case 432: return table_g432();
     case 448: return table_g448();
     case 480: return table_g480();
     case 512: return table_g512();
@@ -122,11 +124,18 @@ k_cg_update(const double2* __restrict__ Q, const double2* __restrict__ P, double
   }
 }
 
-// Assemble an operator result in float32 storage: image block sum_j PR_j + alpha p
-// (p may be null), coil block copied from Q.
+template <class O> __device__ __forceinline__ O out_as(double x, double y);
+template <> __device__ __forceinline__ float2 out_as<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
+}
+template <> __device__ __forceinline__ double2 out_as<double2>(double x, double y) { return make_double2(x, y); }
+
+// Assemble an operator result (complex64 or complex128 storage): image block
+// sum_j PR_j + alpha p (p may be null), coil block copied from Q.
+template <class O>
 __global__ void __launch_bounds__(VT)
 k_finalize(const float2* __restrict__ PR, const double2* __restrict__ p, double alpha,
-           const double2* __restrict__ Q, float2* __restrict__ out, int J, int RR, long long X,
+           const double2* __restrict__ Q, O* __restrict__ out, int J, int RR, long long X,
            int nchunk) {
   const int b = blockIdx.x / nchunk, c = blockIdx.x - b * nchunk;
   const long long e0 = (long long)c * CHUNK;
@@ -145,9 +154,9 @@ k_finalize(const float2* __restrict__ PR, const double2* __restrict__ p, double 
         sx += alpha * pp.x;
         sy += alpha * pp.y;
       }
-      out[ve] = make_float2((float)sx, (float)sy);
+      out[ve] = out_as<O>(sx, sy);
     } else {
-      out[ve] = tof(Q[ve]);
+      out[ve] = out_as<O>(Q[ve].x, Q[ve].y);
     }
   }
 }
@@ -505,8 +514,15 @@ hipError_t launch_channel_cov(const Shape& s, hipStream_t st, const float2* y0, 
 
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
                            double alpha, float2* out, bool image_block) {
-  k_finalize<<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J, s.R * s.R, s.X,
-                                         s.NCH);
+  k_finalize<float2><<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J,
+                                                 s.R * s.R, s.X, s.NCH);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
+                           double alpha, double2* out, bool image_block) {
+  k_finalize<double2><<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J,
+                                                  s.R * s.R, s.X, s.NCH);
   return hipGetLastError();
 }
 
@@ -598,6 +614,173 @@ hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float
   // F^H F = (1/R^2) psf-convolution; the unnormalised 2D DFT pair contributes 1/G^2
   const double scale = 1.0 / ((double)s.G * s.G * (double)s.R * s.R);
   return t->psf_fft(s, w, st, w.P + (size_t)turn * s.G * s.G, scale);
+}
+
+// ---------------------------------------------------------------------------
+// Kaiser-Bessel gridding table of one turn, built on the device: for every
+// grid point p = uy * G + ux of the G x G grid (DC at 0, periodic) the samples
+// s whose kernel reaches it (within half a kernel width on both axes), with
+// the weights phi(ux - G kx_s) phi(uy - G ky_s) rounded to float32, in sample
+// order; and the grid points split into short rows (at most KB_SHORT
+// entries, ascending from the front of the point list) and long rows
+// (ascending from its back).  Count, scan, fill, then a sort of every row by
+// sample index, so the table does not depend on the order in which the
+// fill's atomics land.
+// ---------------------------------------------------------------------------
+
+// visit(p, w) for every grid point that sample s reaches.
+template <class F>
+__device__ inline void kb_taps(const float* __restrict__ traj, int s, int G, double beta, F visit) {
+  const double x = (double)G * traj[2 * s], y = (double)G * traj[2 * s + 1];
+  const int ux0 = (int)ceil(x - 0.5 * KB_W), uy0 = (int)ceil(y - 0.5 * KB_W);
+  double wx[KB_TAPS], wy[KB_TAPS];
+#pragma unroll
+  for (int a = 0; a < KB_TAPS; ++a) {
+    wx[a] = kb_phi(ux0 + a - x, beta);
+    wy[a] = kb_phi(uy0 + a - y, beta);
+  }
+  for (int by = 0; by < KB_TAPS; ++by) {
+    if (wy[by] == 0.0) continue;
+    const int py = ((uy0 + by) % G + G) % G;
+    for (int bx = 0; bx < KB_TAPS; ++bx) {
+      if (wx[bx] == 0.0) continue;
+      const int px = ((ux0 + bx) % G + G) % G;
+      visit(py * G + px, (float)(wy[by] * wx[bx]));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(VT) k_fill_ints(int* __restrict__ p, long long n, int v) {
+  for (long long i = (long long)blockIdx.x * VT + threadIdx.x; i < n; i += (long long)gridDim.x * VT) p[i] = v;
+}
+
+// entries per grid point: cnt[p] += 1 per tap
+__global__ void __launch_bounds__(VT)
+k_kb_count(const float* __restrict__ traj, int S, int G, double beta, int* __restrict__ cnt) {
+  const int s = blockIdx.x * VT + threadIdx.x;
+  if (s >= S) return;
+  kb_taps(traj, s, G, beta, [&](int p, float) { atomicAdd(&cnt[p], 1); });
+}
+
+// One block: rp[1..GG] counts -> row ends (inclusive sums), the point list and
+// the (short, long) point counts.  Thread t owns the points of one contiguous
+// chunk; exclusive block scans of the chunk sums give its offsets.
+constexpr int KB_SCAN_T = 1024;
+
+__global__ void __launch_bounds__(KB_SCAN_T)
+k_kb_scan(int* __restrict__ rp, int* __restrict__ pts, int2* __restrict__ counts, int GG) {
+  __shared__ int sh[2][KB_SCAN_T];
+  const int t = threadIdx.x;
+  const int chunk = (GG + KB_SCAN_T - 1) / KB_SCAN_T;
+  const int p0 = min(GG, t * chunk), p1 = min(GG, p0 + chunk);
+  int sum = 0, nshort = 0;
+  for (int p = p0; p < p1; ++p) {
+    const int c = rp[p + 1];
+    sum += c;
+    nshort += c <= KB_SHORT;
+  }
+  sh[0][t] = sum;
+  sh[1][t] = nshort;
+  __syncthreads();
+  for (int off = 1; off < KB_SCAN_T; off <<= 1) {
+    const int a = t >= off ? sh[0][t - off] : 0, b = t >= off ? sh[1][t - off] : 0;
+    __syncthreads();
+    sh[0][t] += a;
+    sh[1][t] += b;
+    __syncthreads();
+  }
+  int end = sh[0][t] - sum;              // entries before p0
+  int qs = sh[1][t] - nshort;            // short points before p0
+  int ql = p0 - qs;                      // long points before p0
+  for (int p = p0; p < p1; ++p) {
+    const int c = rp[p + 1];
+    end += c;
+    rp[p + 1] = end;
+    if (c <= KB_SHORT) pts[qs++] = p;
+    else pts[GG - 1 - ql++] = p;
+  }
+  if (t == 0) {
+    const int ns = sh[1][KB_SCAN_T - 1];
+    rp[0] = 0;
+    counts[0] = make_int2(ns, GG - ns);
+  }
+}
+
+// entries into their rows, in arrival order
+__global__ void __launch_bounds__(VT)
+k_kb_fill(const float* __restrict__ traj, int S, int G, double beta, const int* __restrict__ rp,
+          int* __restrict__ cur, int2* __restrict__ stage) {
+  const int s = blockIdx.x * VT + threadIdx.x;
+  if (s >= S) return;
+  kb_taps(traj, s, G, beta, [&](int p, float wt) {
+    const int k = rp[p] + atomicAdd(&cur[p], 1);
+    stage[k] = make_int2(s, __float_as_int(wt));
+  });
+}
+
+// short rows: one thread each, odd-even transposition sort in registers
+__global__ void __launch_bounds__(VT)
+k_kb_sort_short(const int* __restrict__ rp, const int2* __restrict__ stage, int2* __restrict__ ent, int GG) {
+  const int p = blockIdx.x * VT + threadIdx.x;
+  if (p >= GG) return;
+  const int e0 = rp[p], n = rp[p + 1] - e0;
+  if (n > KB_SHORT) return;
+  int2 v[KB_SHORT];
+#pragma unroll
+  for (int k = 0; k < KB_SHORT; ++k) v[k] = k < n ? stage[e0 + k] : make_int2(0x7fffffff, 0);
+#pragma unroll
+  for (int r = 0; r < KB_SHORT; ++r) {
+#pragma unroll
+    for (int k = r & 1; k + 1 < KB_SHORT; k += 2) {
+      if (v[k].x > v[k + 1].x) {
+        const int2 tmp = v[k];
+        v[k] = v[k + 1];
+        v[k + 1] = tmp;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KB_SHORT; ++k)
+    if (k < n) ent[e0 + k] = v[k];
+}
+
+// long rows: one wavefront each (grid-stride over the long points), every
+// entry placed at its rank (sample indices of a row are distinct)
+__global__ void __launch_bounds__(VT)
+k_kb_sort_long(const int* __restrict__ rp, const int* __restrict__ pts, const int2* __restrict__ counts,
+               const int2* __restrict__ stage, int2* __restrict__ ent, int GG) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * (VT / 64);
+  const int nl = counts[0].y;
+  for (int q = blockIdx.x * (VT / 64) + (int)(threadIdx.x >> 6); q < nl; q += nw) {
+    const int p = pts[GG - 1 - q];
+    const int e0 = rp[p], n = rp[p + 1] - e0;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+      const int i = i0 + lane;
+      const int2 v = i < n ? stage[e0 + i] : make_int2(0, 0);
+      int rank = 0;
+      for (int j = 0; j < n; ++j) rank += stage[e0 + j].x < v.x;
+      if (i < n) ent[e0 + rank] = v;
+    }
+  }
+}
+
+hipError_t launch_kb_table(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn) {
+  if (!s.kb || S < 1 || S > s.S || turn < 0 || turn >= s.U) return hipErrorInvalidValue;
+  const int G = s.G, GG = G * G;
+  int* rp = w.kbr + (size_t)turn * ((size_t)GG + 1);
+  int2* ent = w.kbe + (size_t)turn * s.kbe_stride;
+  int* pts = w.kbp + (size_t)turn * GG;
+  const double beta = kb_beta();
+  const int fb = (GG + 1 + VT - 1) / VT < 1024 ? (GG + 1 + VT - 1) / VT : 1024;
+  k_fill_ints<<<fb, VT, 0, st>>>(rp, (long long)GG + 1, 0);
+  k_fill_ints<<<fb, VT, 0, st>>>(w.kbq, (long long)GG, 0);
+  k_kb_count<<<(S + VT - 1) / VT, VT, 0, st>>>(traj, S, G, beta, rp + 1);
+  k_kb_scan<<<1, KB_SCAN_T, 0, st>>>(rp, pts, w.kbn + turn, GG);
+  k_kb_fill<<<(S + VT - 1) / VT, VT, 0, st>>>(traj, S, G, beta, rp, w.kbq, w.kbs);
+  k_kb_sort_short<<<(GG + VT - 1) / VT, VT, 0, st>>>(rp, w.kbs, ent, GG);
+  k_kb_sort_long<<<KB_LONG_BLOCKS, VT, 0, st>>>(rp, pts, w.kbn + turn, w.kbs, ent, GG);
+  return hipGetLastError();
 }
 
 }  // namespace nlv

@@ -75,6 +75,12 @@ def load() -> ctypes.CDLL:
         "nlinv_apply_DFH": [_P, _P, _P, _P, _P],
         "nlinv_apply_normal": [_P, _P, _P, ctypes.c_double, _P, _P],
         "nlinv_apply_WH": [_P, _P, _P],
+        "nlinv_apply_normal2": [_P, _P, _P, _P, ctypes.c_double, _P, _P],
+        "nlinv_apply_E": [_P, _P, _P, _P],
+        "nlinv_apply_EH": [_P, _P, _P, _P],
+        "nlinv_nudft": [_P, _P, _P, _P],
+        "nlinv_newton_step": [_P, _P, _P, _P, ctypes.c_double, _I, _P],
+        "nlinv_set_coil_weights": [_P, _P],
         "nlinv_compress": [_P, _P, _I, _P, _P],
         "nlinv_compression_matrix": [_P, _P, _I, _P],
         "nlinv_coils": [_P, _P, _P, _P],
@@ -160,6 +166,7 @@ class Plan:
         sz = sizes(self.params)
         self.N, self.J, self.K = N, J, K
         self.R, self.G, self.Gc, self.S, self.X = sz["R"], sz["G"], sz["Gc"], sz["S"], sz["X"]
+        self.dtype = torch.complex64        # precision of the unknowns and linearisation points
         self.B = self.params.batch          # active batch (set_batch)
         self.Bmax = self.params.batch
         self.U = self.params.U
@@ -392,6 +399,74 @@ class Plan:
         _check(self.lib.nlinv_apply_normal(self.handle, self._turns(turns), self._ptr(xhat), float(alpha),
                                            self._ptr(p), self._ptr(q)), self.handle)
         return q
+
+    def apply_normal2(self, turns, xa, xb, p, alpha: float = 0.0, q=None):
+        """q = DF_xa^H DF_xb p + alpha p through the PSF convolution; p, q complex128 [B][X]."""
+        torch = self.torch
+        self._t(xa, torch.complex64, (self.B, self.X), "xa")
+        self._t(xb, torch.complex64, (self.B, self.X), "xb")
+        self._t(p, torch.complex128, (self.B, self.X), "p")
+        q = self.empty(self.B, self.X, dtype=torch.complex128) if q is None else q
+        self._t(q, torch.complex128, (self.B, self.X), "q")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_normal2(self.handle, self._turns(turns), self._ptr(xa), self._ptr(xb),
+                                            float(alpha), self._ptr(p), self._ptr(q)), self.handle)
+        return q
+
+    def apply_E(self, xhat, p, img=None):
+        """Image-space derivative E_x p [B][J][R][R] (complex64) of p complex128 [B][X]."""
+        torch = self.torch
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(p, torch.complex128, (self.B, self.X), "p")
+        img = self.empty(self.B, self.J, self.R, self.R) if img is None else img
+        self._t(img, torch.complex64, (self.B, self.J, self.R, self.R), "img")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_E(self.handle, self._ptr(xhat), self._ptr(p), self._ptr(img)), self.handle)
+        return img
+
+    def apply_EH(self, xhat, img, out=None):
+        """E_x^H img, complex128 [B][X], of images [B][J][R][R] complex64."""
+        torch = self.torch
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(img, torch.complex64, (self.B, self.J, self.R, self.R), "img")
+        out = self.empty(self.B, self.X, dtype=torch.complex128) if out is None else out
+        self._t(out, torch.complex128, (self.B, self.X), "out")
+        self._stream_sync()
+        _check(self.lib.nlinv_apply_EH(self.handle, self._ptr(xhat), self._ptr(img), self._ptr(out)), self.handle)
+        return out
+
+    def nudft(self, traj, img, y=None):
+        """y = F img per channel [B][J][S] (exact non-uniform DFT)."""
+        torch = self.torch
+        self._t(traj, torch.float32, (self.B, self.K, self.S_r, 2), "traj")
+        self._t(img, torch.complex64, (self.B, self.J, self.R, self.R), "img")
+        y = self.empty(self.B, self.J, self.S) if y is None else y
+        self._t(y, torch.complex64, (self.B, self.J, self.S), "y")
+        self._stream_sync()
+        _check(self.lib.nlinv_nudft(self.handle, self._ptr(traj), self._ptr(img), self._ptr(y)), self.handle)
+        return y
+
+    def newton_step(self, turns, z, xhat, alpha: float, cg: int, xprev=None):
+        """One IRGNM update of xhat [B][X] complex64 in place (nlinv_newton_step)."""
+        torch = self.torch
+        self._t(z, torch.complex64, (self.B, self.J, self.R, self.R), "z")
+        self._t(xhat, torch.complex64, (self.B, self.X), "xhat")
+        self._t(xprev, torch.complex64, (self.B, self.X), "xprev", allow_none=True)
+        self._stream_sync()
+        _check(self.lib.nlinv_newton_step(self.handle, self._turns(turns), self._ptr(z), self._ptr(xprev),
+                                          float(alpha), int(cg), self._ptr(xhat)), self.handle)
+        return xhat
+
+    def set_coil_weights(self, winv=None):
+        """Use the table winv [Gc][Gc] of 1 / (G w') (stored as float32) as the
+        Sobolev weight from now on (None: the plan's own).  The binding keeps
+        the table alive while it is set."""
+        torch = self.torch
+        if winv is not None:
+            winv = winv.to(device=self.device, dtype=torch.float32).contiguous()
+        self._t(winv, torch.float32, (self.Gc, self.Gc), "winv", allow_none=True)
+        _check(self.lib.nlinv_set_coil_weights(self.handle, self._ptr(winv)), self.handle)
+        self._winv = winv
 
     def coils(self, xhat, coils=None, img=None, want_img: bool = True):
         torch = self.torch

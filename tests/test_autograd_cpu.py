@@ -13,12 +13,44 @@ from paper_1701_08361_amd import synth
 
 
 class OracleOps:
-    """apply_F / apply_DF / apply_DFH, coils and apply_WH in the shapes of the
-    C-ABI binding, FP64."""
+    """apply_F / apply_DF / apply_DFH, coils, apply_WH and the operators of the
+    Toeplitz form (grid, nudft, apply_normal2, apply_E, apply_EH) in the shapes
+    of the C-ABI binding, FP64.  `turn_trajs[t]` is the trajectory [K][S_r][2]
+    whose PSF kernel stands at turn t."""
 
-    def __init__(self, g):
+    dtype = torch.complex128
+
+    def __init__(self, g, turn_trajs=None):
         self.g = g
         self.X = g.X
+        self.P = {}
+        if turn_trajs is not None:
+            for t, tr in enumerate(np.asarray(turn_trajs, np.float64)):
+                self.P[t] = O.psf_kernel(tr, g.R, g.G)
+
+    def grid(self, traj, y):
+        return self._each(lambda t, v: O.grid(v, t, self.g.R), traj, y)
+
+    def nudft(self, traj, img):
+        return self._each(lambda t, u: O.nudft(u, t), traj, img)
+
+    def apply_E(self, x, p):
+        g = self.g
+
+        def one(x, p):
+            rho, _ = g.unpack(x)
+            drho, dchat = g.unpack(p)
+            return g.coils(x) * drho[None] + rho[None] * O.winv(dchat, g.G, g.R, g.w)
+        return self._each(one, x, p)
+
+    def apply_EH(self, x, img):
+        return self._each(lambda x, t: O.image_adjoint(self.g, x, t), x, img)
+
+    def apply_normal2(self, turns, xa, xb, p, alpha=0.0):
+        u = self.apply_E(xb, p)
+        t = torch.from_numpy(np.stack([O.toeplitz(u[b].numpy(), self.P[int(turns[b])])
+                                       for b in range(u.shape[0])]))
+        return self.apply_EH(xa, t) + alpha * p.detach()
 
     def coils(self, xhat, want_img=False):
         return self._each(lambda x: self.g.coils(x), xhat), None
@@ -102,7 +134,8 @@ def test_unrolled_equals_oracle_reconstruction():
     s = synth.single_frame(seed=5, N=8, J=2, K=5)
     t = s.traj.astype(np.float64)
     y = torch.from_numpy(s.y.astype(np.complex128))
-    x = UR.reconstruct(ops, torch.from_numpy(t), y, g.R, newton=3, cg_iters=4, checkpoint_steps=True)
+    x = UR.reconstruct(ops, torch.from_numpy(t), y, g.R, newton=3, cg_iters=4, checkpoint_steps=True,
+                       form="nudft")
     P = O.psf_kernel(t[0], g.R, g.G)
     ref = O.reconstruct(g, O.grid(s.y[0].astype(np.complex128), t[0], g.R), P, newton=3, cg_iters=4)
     err = np.linalg.norm(x.numpy()[0] - ref) / np.linalg.norm(ref)
@@ -118,7 +151,7 @@ def test_unrolled_gradcheck_data_and_alpha():
     a0 = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
 
     def fn(y, a0):
-        x = UR.reconstruct(ops, traj[:1], y, g.R, newton=2, cg_iters=2, alpha0=a0)
+        x = UR.reconstruct(ops, traj[:1], y, g.R, newton=2, cg_iters=2, alpha0=a0, form="nudft")
         return UR.image(ops, x, g.R)
 
     assert torch.autograd.gradcheck(fn, (y, a0), eps=1e-6, atol=1e-5, rtol=1e-4)
@@ -172,7 +205,7 @@ def test_unrolled_reweighted_equals_oracle_reconstruction():
     s = synth.single_frame(seed=5, N=8, J=2, K=5)
     t = s.traj.astype(np.float64)
     y = torch.from_numpy(s.y.astype(np.complex128))
-    x = UR.reconstruct(_reweighted(ops, g), torch.from_numpy(t), y, g.R, newton=3, cg_iters=4)
+    x = UR.reconstruct(_reweighted(ops, g), torch.from_numpy(t), y, g.R, newton=3, cg_iters=4, form="nudft")
     P = O.psf_kernel(t[0], g2.R, g2.G)
     ref = O.reconstruct(g2, O.grid(s.y[0].astype(np.complex128), t[0], g2.R), P, newton=3, cg_iters=4)
     err = np.linalg.norm(x.detach().numpy()[0] - ref) / np.linalg.norm(ref)
@@ -193,11 +226,177 @@ def test_unrolled_gradcheck_sobolev_weight():
 
     def fn(a, l):
         m = AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
-        x = UR.reconstruct(m, traj[:1], y, g.R, newton=2, cg_iters=2)
+        x = UR.reconstruct(m, traj[:1], y, g.R, newton=2, cg_iters=2, form="nudft")
         return UR.image(m, x, g.R)
 
     # the weight reaches the image: a gradient far from zero is checked
     ga, gl = torch.autograd.grad(fn(a, l).sum(), (a, l))
     print(f"d sum(image) / d(a, l) = {float(ga):.3e}, {float(gl):.3e}")
     assert abs(float(ga)) > 1e-4 and abs(float(gl)) > 1e-3
+    assert torch.autograd.gradcheck(fn, (a, l), eps=1e-5, atol=1e-6, rtol=1e-4)
+
+
+# --------------------------------------------------------------------------
+# the Toeplitz form: z = F^H y, E_x^H, and E_x^H T E_x + alpha with their
+# hand-written backward rules
+# --------------------------------------------------------------------------
+
+class OracleSolverOps(OracleOps):
+    """OracleOps with the solver's Newton step (the oracle's, FP64) and a
+    settable coil-weight table, in the interface of the library plan: the
+    unrolled form then takes its library-step path."""
+
+    def __init__(self, g, turn_trajs=None):
+        super().__init__(g, turn_trajs)
+        self.g_own = g
+
+    def set_coil_weights(self, winv=None):
+        g = self.g_own
+        if winv is None:
+            self.g = g
+        else:
+            w = 1.0 / (g.G * winv.detach().numpy().astype(np.float64))
+            self.g = O.Geometry(R=g.R, G=g.G, Gc=g.Gc, J=g.J, w=w)
+
+    def newton_step(self, turns, z, xhat, alpha, cg, xprev=None):
+        for b in range(xhat.shape[0]):
+            x = xhat[b].numpy()
+            xp = self.g.initial() if xprev is None else xprev[b].numpy()
+            h = O.newton_step(self.g, x, xp, z[b].detach().numpy(), self.P[int(turns[b])], alpha, cg)
+            xhat[b] = torch.from_numpy(x + h)
+        return xhat
+
+
+def _toeplitz_setup(B=2, N=8, J=2, K=3, seed=0):
+    ops, traj, g, cx = _setup(B=B, N=N, J=J, K=K, seed=seed)
+    return OracleOps(g, traj.numpy()), traj, g, cx
+
+
+def test_oracle_ops_normal2_is_the_nudft_normal_operator():
+    """The stand-in's E_x^H T E_x p equals DF^H DF p through the exact DFT
+    (T = F^H F), and E_x^H img / E_x p equal the parts of DF^H / DF."""
+    ops, traj, g, cx = _toeplitz_setup(B=2, seed=20)
+    x, p = cx(2, g.X), cx(2, g.X)
+    q = ops.apply_normal2([0, 1], x, x, p, 0.25)
+    ref = ops.apply_DFH(traj, x, ops.apply_DF(traj, x, p)) + 0.25 * p
+    assert float(torch.linalg.norm(q - ref) / torch.linalg.norm(ref)) < 1e-12
+    v = cx(2, g.J, traj.shape[1] * traj.shape[2])
+    assert torch.allclose(ops.apply_EH(x, ops.grid(traj, v)), ops.apply_DFH(traj, x, v), rtol=1e-12, atol=1e-12)
+    assert torch.allclose(ops.nudft(traj, ops.apply_E(x, p)), ops.apply_DF(traj, x, p), rtol=1e-12, atol=1e-12)
+
+
+def test_grid_gradcheck():
+    ops, traj, g, cx = _toeplitz_setup(seed=21)
+    y = cx(2, g.J, traj.shape[1] * traj.shape[2]).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda y: AG.grid(ops, traj, y), (y,), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_EH_gradcheck():
+    ops, traj, g, cx = _toeplitz_setup(seed=22)
+    x = cx(2, g.X).requires_grad_(True)
+    img = cx(2, g.J, g.R, g.R).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x, v: AG.EH(ops, x, v), (x, img), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_normal_gradcheck():
+    """x, p and alpha of E_x^H T E_x p + alpha p, the second-order rule in x
+    included."""
+    ops, traj, g, cx = _toeplitz_setup(seed=23)
+    x = cx(2, g.X).requires_grad_(True)
+    p = cx(2, g.X).requires_grad_(True)
+    a = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x, p, a: AG.normal(ops, [0, 1], x, p, a), (x, p, a), eps=1e-6,
+                                    atol=1e-6, rtol=1e-5)
+
+
+def test_reweighted_normal_and_EH_equal_the_oracle_at_that_weight():
+    ops, traj, g, cx = _toeplitz_setup(B=2, seed=24)
+    g2 = O.Geometry.make(8, 2, a=A_W, l=L_W)
+    ops2 = OracleOps(g2, traj.numpy())
+    m = _reweighted(ops, g)
+    x, p = cx(2, g.X), cx(2, g.X)
+    img = cx(2, g.J, g.R, g.R)
+    rel = lambda u, v: float(torch.linalg.norm(u - v) / torch.linalg.norm(v))
+    assert rel(m.normal([0, 1], x, p, 0.5), ops2.apply_normal2([0, 1], x, x, p, 0.5)) < 1e-12
+    assert rel(m.EH(x, img), ops2.apply_EH(x, img)) < 1e-12
+
+
+@pytest.mark.parametrize("solver_step", [False, True])
+@pytest.mark.parametrize("reweighted", [False, True])
+def test_unrolled_toeplitz_equals_oracle_reconstruction(reweighted, solver_step):
+    """The Toeplitz form (the solver's own) reproduces the oracle's IRGNM, with
+    the reference weight and with (20, 2) rebuilt from the (880, 16) operators."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _setup(B=1, N=8, J=2, K=5, seed=5)
+    s = synth.single_frame(seed=5, N=8, J=2, K=5)
+    t = s.traj.astype(np.float64)
+    ops = (OracleSolverOps if solver_step else OracleOps)(g, t)
+    g2 = O.Geometry.make(8, 2, a=A_W, l=L_W) if reweighted else g
+    m = _reweighted(ops, g) if reweighted else ops
+    y = torch.from_numpy(s.y.astype(np.complex128))
+    x = UR.reconstruct(m, torch.from_numpy(t), y, g.R, newton=3, cg_iters=4, turns=[0])
+    assert x.dtype == torch.complex128
+    P = O.psf_kernel(t[0], g.R, g.G)
+    ref = O.reconstruct(g2, O.grid(s.y[0].astype(np.complex128), t[0], g.R), P, newton=3, cg_iters=4)
+    err = np.linalg.norm(x.detach().numpy()[0] - ref) / np.linalg.norm(ref)
+    assert err < 1e-9, err
+
+
+@pytest.mark.parametrize("solver_step", [False, True])
+def test_unrolled_toeplitz_gradcheck_data_and_alpha(solver_step):
+    """(with solver_step: forward by the solver's Newton step, backward by the
+    recomputed differentiable step)"""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _toeplitz_setup(B=1, N=8, J=2, K=3, seed=6)
+    if solver_step:
+        ops = OracleSolverOps(g, traj.numpy())
+    y = (0.3 * cx(1, g.J, traj.shape[1] * traj.shape[2])).requires_grad_(True)
+    a0 = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+
+    def fn(y, a0):
+        x = UR.reconstruct(ops, traj[:1], y, g.R, newton=2, cg_iters=2, alpha0=a0, turns=[0])
+        return UR.image(ops, x, g.R)
+
+    assert torch.autograd.gradcheck(fn, (y, a0), eps=1e-6, atol=1e-5, rtol=1e-4)
+
+
+def test_unrolled_toeplitz_gradients_equal_the_nudft_form():
+    """Both forms compute the same iterates; their gradients with respect to
+    y, alpha_0, a and l agree to rounding."""
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _toeplitz_setup(B=1, N=8, J=2, K=3, seed=8)
+    y0 = 0.3 * cx(1, g.J, traj.shape[1] * traj.shape[2])
+
+    def grads(form):
+        y = y0.clone().requires_grad_(True)
+        a0 = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+        a = torch.tensor(A_W, dtype=torch.float64, requires_grad=True)
+        l = torch.tensor(L_W, dtype=torch.float64, requires_grad=True)
+        m = AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
+        x = UR.reconstruct(m, traj[:1], y, g.R, newton=3, cg_iters=3, alpha0=a0, form=form, turns=[0])
+        UR.image(m, x, g.R).pow(2).sum().backward()
+        return [y.grad, a0.grad, a.grad, l.grad]
+
+    for u, v in zip(grads("toeplitz"), grads("nudft")):
+        assert float(torch.linalg.norm(u - v) / torch.linalg.norm(v)) < 1e-9
+    ops = OracleSolverOps(g, traj.numpy())
+    for u, v in zip(grads("toeplitz"), grads("nudft")):
+        assert float(torch.linalg.norm(u - v) / torch.linalg.norm(v)) < 1e-9
+
+
+@pytest.mark.parametrize("solver_step", [False, True])
+def test_unrolled_toeplitz_gradcheck_sobolev_weight(solver_step):
+    from paper_1701_08361_amd import unrolled as UR
+    ops, traj, g, cx = _toeplitz_setup(B=1, N=8, J=2, K=3, seed=7)
+    if solver_step:
+        ops = OracleSolverOps(g, traj.numpy())
+    y = 0.3 * cx(1, g.J, traj.shape[1] * traj.shape[2])
+    a = torch.tensor(A_W, dtype=torch.float64, requires_grad=True)
+    l = torch.tensor(L_W, dtype=torch.float64, requires_grad=True)
+
+    def fn(a, l):
+        m = AG.Reweighted(ops, g.G, g.Gc, g.R, g.J, a, l)
+        x = UR.reconstruct(m, traj[:1], y, g.R, newton=2, cg_iters=2, turns=[0])
+        return UR.image(m, x, g.R)
+
     assert torch.autograd.gradcheck(fn, (a, l), eps=1e-5, atol=1e-6, rtol=1e-4)

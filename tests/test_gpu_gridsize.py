@@ -31,6 +31,7 @@ def rel(a, b):
 @pytest.mark.parametrize("N,G,J,K,M,C", [
     (48, 128, 6, 11, 4, 8),      # gamma 4/3, 64 x 64 field of view
     (40, 128, 4, 9, 3, 6),       # gamma 1.6, image centre at offset 12
+    (144, 432, 4, 9, 2, 3),      # Table oversampling_ratio, N = 144 on the paper's 432 grid (gamma 1.5)
     (160, 480, 4, 9, 2, 3),      # Table oversampling_ratio, N = 160 at the fixed gamma = 1.5
     (170, 512, 4, 9, 2, 3),      # Table oversampling_ratio, N = 170 at its chosen 512 grid
 ])

@@ -92,6 +92,40 @@ def test_grid_matches_exact_adjoint_nudft(torch, N, J, K, seed):
         assert rel(z[0], ref) < 1e-6
 
 
+def test_grid_tables_are_reproducible_and_handle_long_rows(torch):
+    """The per-turn gridding tables are built on the device (count, scan,
+    atomic fill, per-row sort by sample index): rebuilding a turn, building it
+    in another plan, or after another trajectory gives the same gridded data
+    bit for bit; and a trajectory whose 15 spokes coincide (rows of ~135
+    entries, more than one wavefront's width) grids to the exact sum."""
+    N, J, K = 64, 4, 15
+    print_case("grid tables", N=N, J=J, K=K)
+    s = synth.single_frame(seed=21, N=N, J=J, K=K)
+    s2 = synth.single_frame(seed=22, N=N, J=J, K=K)
+    tr, y = dev(torch, s.traj), dev(torch, s.y)
+    plan = nl().Plan(N, J, K)
+    z0 = host(plan.grid(tr, y, turns=[0]))
+    plan.psf(tr[0], 0)
+    z1 = host(plan.grid(tr, y, turns=[0]))
+    plan.psf(dev(torch, s2.traj[0]), 0)
+    plan.psf(tr[0], 0)
+    z2 = host(plan.grid(tr, y, turns=[0]))
+    other = nl().Plan(N, J, K, U=2)
+    other.psf(dev(torch, s2.traj[0]), 0)
+    z3 = host(other.grid(tr, y, turns=[1]))
+    assert np.array_equal(z0, z1) and np.array_equal(z0, z2) and np.array_equal(z0, z3)
+    # coinciding spokes
+    same = np.repeat(s.traj[0][:1], K, axis=0)[None]
+    ref = O.grid(s.y[0], same[0], N)
+    plan2 = nl().Plan(N, J, K)
+    z = host(plan2.grid(dev(torch, same), y, turns=[0]))
+    zb = host(plan2.grid(dev(torch, same), y, turns=[0]))
+    print(f"coinciding spokes: rel {rel(z[0], ref):.2e}")
+    assert rel(z[0], ref) < 1e-6 and np.array_equal(z, zb)
+    for p_ in (plan, other, plan2):
+        p_.close()
+
+
 @pytest.mark.parametrize("N,J", [(32, 2), (64, 8), (128, 5), (160, 10), (192, 3), (224, 4), (240, 3), (256, 2)])
 def test_coil_synthesis(torch, N, J):
     print_case("coils", N=N, J=J)
@@ -131,6 +165,7 @@ def _normal_case(torch, N, J, K, U, B, alpha, seed):
 @pytest.mark.parametrize("N,J,K,U,B,alpha", [
     (32, 2, 5, 1, 1, 0.0), (64, 8, 13, 2, 3, 0.37), (64, 8, 13, 1, 1, 0.0),
     (128, 4, 11, 3, 2, 0.0), (160, 10, 15, 5, 2, 0.125), (192, 3, 9, 1, 1, 0.0),
+    (216, 4, 13, 2, 2, 0.3),    # 432 grid (16 x 27 team transform)
     (224, 5, 21, 2, 2, 0.5), (240, 3, 9, 1, 1, 0.25), (256, 2, 11, 2, 2, 0.0),
     (32, 64, 5, 2, 2, 0.1),     # the most channels a plan takes
     (32, 2, 3, 4, 64, 0.0)])    # the largest batch
@@ -208,6 +243,7 @@ def test_reconstruct_single_frame_c1(torch):
 @pytest.mark.parametrize("N,J,K,M,C", [
     (128, 8, 11, 4, 8),     # smallest mixed-size configuration (256 grid)
     (192, 16, 21, 3, 6),    # largest mixed-size configuration (384 grid, 16 coils, 21 spokes)
+    (216, 6, 13, 2, 4),     # 432 grid (16 x 27)
     (224, 16, 21, 2, 4),    # 448 grid, 16 coils
     (256, 4, 9, 2, 3),      # largest supported grid (512)
     (32, 1, 1, 3, 4),       # degenerate: one coil, one spoke

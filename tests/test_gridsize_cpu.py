@@ -32,7 +32,7 @@ def _printed_rows():
 
 
 def test_supported_grids_come_from_the_library(lib):
-    assert GS.supported_grids(nl) == [64, 128, 256, 320, 384, 448, 480, 512]
+    assert GS.supported_grids(nl) == [64, 128, 256, 320, 384, 432, 448, 480, 512]
 
 
 @pytest.mark.parametrize("N,G,expect", [
