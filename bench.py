@@ -507,7 +507,7 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
     for frames in frame_counts:
         frames = min(frames, traj_all.shape[0])
         p = dict(mode="single-slice", N=N, J=J, K=K, U=U, frames=frames, newton=M, cg=C)
-        tuner = AT.Autotuner(db, learning=True, tiles=(8, 4))
+        tuner = AT.Autotuner(db, learning=True, tiles=(8, 4), passes=(6, 4))
         if not graphs_allowed:
             tuner.space = [c for c in tuner.space if not c["graphs"]]
         tuner.learn(p, lambda c: AT.run_series(nl, torch, traj_all[:frames], y_all[:frames],
@@ -516,11 +516,11 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
         (bc, bf), (wc, wf) = hits[0], hits[-1]
         rows.append({"frames": frames, "settings": len(hits),
                      "worst": dict(wc, fps=wf), "best": dict(bc, fps=bf),
-                     "all": [[c["T"], c["graphs"], c["col_tile"], round(f, 1)] for c, f in hits]})
+                     "all": [[c["T"], c["graphs"], c["col_tile"], c["cg_passes"], round(f, 1)] for c, f in hits]})
     return {"form": "learning mode over T = 1..8 frames per relaxed group (l = 5 strict frames first), A = 1, "
-                    "HIP graphs off/on, column-pass tile schedule 8 or 4 columns per block; rate = frames / "
-                    "wall time of the whole series (gridding + reconstruction); 'all' rows are "
-                    "[T, graphs, col_tile, fps]",
+                    "HIP graphs off/on, column-pass tile schedule 8 or 4 columns per block, CG iteration of 6 or 4 "
+                    "passes; rate = frames / wall time of the whole series (gridding + reconstruction); 'all' "
+                    "rows are [T, graphs, col_tile, cg_passes, fps]",
             "by_frames": rows}
 
 

@@ -22,8 +22,11 @@ decomposition).  On one GPU the setting is
          frames.
 The search space for A = 1 is T = 1..8, as in the paper, times graphs off/on.
 A tuner may also search the tile schedule of the CG column passes
-(col_tile: columns per block, 8 or 4; the same images bit for bit), so that
-the kernel decomposition is measured per protocol instead of fixed.
+(col_tile: columns per block, 8 or 4; the same images bit for bit) and the
+pass fusion of a CG iteration (cg_passes: six dependent kernels, or four with
+the direction update, the coil rows of the direction and the vector step
+folded into the operator's passes; the same images to rounding), so that the
+kernel decomposition is measured per protocol instead of fixed.
 
 The database is a JSON file (a list of records); the runner reconstructs a
 whole series through the C-ABI and measures it with the host clock around
@@ -48,13 +51,17 @@ def _norm_protocol(p: Dict) -> Dict:
     return {k: p[k] for k in PROTOCOL_KEYS}
 
 
-def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] = None) -> List[Dict]:
+def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] = None,
+                 passes: Optional[Sequence[int]] = None) -> List[Dict]:
     """Settings (T, A, graphs): for A = 1, T = 1..max_T; for A = 2 up to
     max_T / 2; for A = 3, 4 up to max_T / 4 (the paper's limits on 8 GPUs),
     with A <= gpus; each with graphs off and on; with `tiles`, each also with
-    every listed column-pass tile schedule (col_tile)."""
+    every listed column-pass tile schedule (col_tile); with `passes`, each
+    also with every listed CG pass fusion (cg_passes, 4 or 6)."""
     if tiles is not None and (not tiles or any(t not in (4, 8) for t in tiles)):
         raise ValueError("tile schedules are 4 or 8 columns per block")
+    if passes is not None and (not passes or any(p not in (4, 6) for p in passes)):
+        raise ValueError("a CG iteration has 4 or 6 passes")
     out = []
     for A in (1, 2, 3, 4):
         if A > gpus:
@@ -62,10 +69,12 @@ def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] =
         tmax = max_T if A == 1 else (max_T // 2 if A == 2 else max(1, max_T // 4))
         for T in range(1, tmax + 1):
             for graphs in (False, True):
-                if tiles is None:
-                    out.append({"T": T, "A": A, "graphs": graphs})
-                else:
-                    out.extend({"T": T, "A": A, "graphs": graphs, "col_tile": int(t)} for t in tiles)
+                base = [{"T": T, "A": A, "graphs": graphs}]
+                if tiles is not None:
+                    base = [dict(c, col_tile=int(t)) for c in base for t in tiles]
+                if passes is not None:
+                    base = [dict(c, cg_passes=int(p)) for c in base for p in passes]
+                out.extend(base)
     return out
 
 
@@ -125,9 +134,9 @@ def protocol_distance(a: Dict, b: Dict) -> float:
 
 class Autotuner:
     def __init__(self, db: TuningDB, gpus: int = 1, max_T: int = 8, learning: bool = False,
-                 tiles: Optional[Sequence[int]] = None):
+                 tiles: Optional[Sequence[int]] = None, passes: Optional[Sequence[int]] = None):
         self.db, self.learning = db, learning
-        self.space = search_space(gpus, max_T, tiles)
+        self.space = search_space(gpus, max_T, tiles, passes)
 
     def untried(self, protocol: Dict) -> List[Dict]:
         tried = [c for c, _ in self.db.lookup(protocol)]
@@ -179,7 +188,8 @@ def run_series(nl, torch, traj, y, turns, config: Dict, newton: int, cg: int, U:
     N = int(round(traj.shape[2] / 2))
     K = traj.shape[1]
     l = U if l is None else l
-    plan = nl.Plan(N, J, K, U=U, batch=T, newton=newton, cg=cg, col_tile=int(config.get("col_tile", 0)))
+    plan = nl.Plan(N, J, K, U=U, batch=T, newton=newton, cg=cg, col_tile=int(config.get("col_tile", 0)),
+                   cg_passes=int(config.get("cg_passes", 0)))
     try:
         plan.set_graphs(bool(config.get("graphs", True)))
         for t in range(min(U, F)):

@@ -92,3 +92,17 @@ def test_database_rejects_bad_records(tmp_path):
     bad.write_text('{"not": "a list"}')
     with pytest.raises(ValueError):
         AT.TuningDB(str(bad))
+
+
+def test_search_space_with_pass_fusion():
+    """With passes, every setting comes with each CG pass fusion; a faster
+    four-pass form is found and recorded."""
+    sp = AT.search_space(1, tiles=(8, 4), passes=(6, 4))
+    assert len(sp) == 64 and {c["cg_passes"] for c in sp} == {4, 6}
+    assert len({tuple(sorted(c.items())) for c in sp}) == 64
+    with pytest.raises(ValueError):
+        AT.search_space(1, passes=(5,))
+    rate = lambda c: fake_rate(c) + (0.25 if c["cg_passes"] == 4 else 0.0) + (0.5 if c["col_tile"] == 4 else 0.0)
+    tuner = AT.Autotuner(AT.TuningDB(), learning=True, tiles=(8, 4), passes=(6, 4))
+    best = tuner.learn(proto(), rate)
+    assert best == {"T": 3, "A": 1, "graphs": True, "col_tile": 4, "cg_passes": 4}

@@ -60,8 +60,12 @@ def test_runner_settings_and_learning(torch, tmp_path):
     e1 = rel(i1.cpu().numpy(), O.image(g, strict[-1]))
     e3 = rel(i3.cpu().numpy(), O.image(g, relaxed[-1]))
     d = rel(O.image(g, relaxed[-1]), O.image(g, strict[-1]))
-    print(f"last frame vs oracle: T=1 {e1:.2e}, T=3 {e3:.2e} (relaxed vs strict {d:.2e})")
-    assert e1 < 1e-3 and e3 < 1e-3 and d > 10 * e3
+    # the four-pass CG iteration changes the rounding, not the method
+    _, i34 = run({"T": 3, "A": 1, "graphs": False, "cg_passes": 4})
+    e34 = rel(i34.cpu().numpy(), O.image(g, relaxed[-1]))
+    print(f"last frame vs oracle: T=1 {e1:.2e}, T=3 {e3:.2e}, T=3 four-pass {e34:.2e} "
+          f"(relaxed vs strict {d:.2e})")
+    assert e1 < 1e-3 and e3 < 1e-3 and e34 < 1e-3 and d > 10 * e3
     # learning over a reduced space records every setting; the choice is the fastest
     db = AT.TuningDB(str(tmp_path / "tune.json"))
     tuner = AT.Autotuner(db, max_T=2, learning=True)
