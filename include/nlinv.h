@@ -333,8 +333,9 @@ int nlinv_compress(nlinv_plan plan, const nlinv_c64* d_cc, int32_t J_phys,
  * the conjugated eigenvectors of the channel covariance y0 y0^H of one frame
  * d_y0 [J_phys][S] for its J largest eigenvalues (principal components; each
  * row is defined up to a phase).  The covariance is formed on the GPU in
- * FP64, the Hermitian eigenproblem (J_phys x J_phys) solved on the host by
- * Jacobi rotations; blocks the host.  J <= J_phys <= 128. */
+ * FP64 and the Hermitian eigenproblem (J_phys x J_phys) solved there by
+ * parallel cyclic Jacobi rotations in one block; the call only enqueues
+ * (d_y0 must stay valid until the work has run).  J <= J_phys <= 128. */
 int nlinv_compression_matrix(nlinv_plan plan, const nlinv_c64* d_y0, int32_t J_phys, nlinv_c64* d_cc);
 
 /* Adjoint of the coil synthesis c_j = W^-1 c_hat_j (Sec. 2.2, Sec. 3.2):

@@ -15,7 +15,6 @@
 #include <string>
 #include <vector>
 
-#include "nlinv_eig.h"
 #include "nlinv_internal.h"
 
 using nlv::Bufs;
@@ -205,7 +204,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   L->KBQ = take(S.kb ? (size_t)Gs * Gs * 4 : 0);
   L->KBC = take(S.kb ? R * 4 : 0);
   L->KG = take(S.kb ? B * J * Gs * Gs * c8 : 0);
-  L->COV = take((size_t)nlv::MAX_JP * nlv::MAX_JP * c16);
+  L->COV = take((size_t)2 * nlv::MAX_JP * nlv::MAX_JP * c16);   // covariance, then its eigenvectors
   L->FLAG = take(sizeof(int));
   L->VR = take(B * J * GC * R * c16);
   L->VP = take(B * J * GC * R * c16);
@@ -1011,25 +1010,8 @@ int nlinv_compression_matrix(nlinv_plan plan, const nlinv_c64* d_y0, int32_t J_p
   const Shape& s = plan->s;
   if (J_phys < s.J || J_phys > nlv::MAX_JP) return fail(plan, NLINV_E_ARG, "J_phys must be in [J, 128]");
   NLV_HIP(plan, nlv::launch_channel_cov(s, plan->stream, reinterpret_cast<const float2*>(d_y0), J_phys, plan->w.cov));
-  std::vector<double2> cov((size_t)J_phys * J_phys);
-  NLV_HIP(plan, hipMemcpyAsync(cov.data(), plan->w.cov, cov.size() * sizeof(double2), hipMemcpyDeviceToHost,
-                               plan->stream));
-  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
-  std::vector<std::complex<double>> A(cov.size()), V;
-  for (size_t i = 0; i < cov.size(); ++i) A[i] = std::complex<double>(cov[i].x, cov[i].y);
-  std::vector<double> ev;
-  nlv::hermitian_eig(J_phys, A, ev, V);
-  std::vector<int> order(J_phys);
-  for (int i = 0; i < J_phys; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] > ev[b]; });
-  std::vector<float2> cc((size_t)s.J * J_phys);
-  for (int j = 0; j < s.J; ++j)
-    for (int p = 0; p < J_phys; ++p) {
-      const std::complex<double> v = std::conj(V[(size_t)p * J_phys + order[j]]);
-      cc[(size_t)j * J_phys + p] = make_float2((float)v.real(), (float)v.imag());
-    }
-  NLV_HIP(plan, hipMemcpyAsync(d_cc, cc.data(), cc.size() * sizeof(float2), hipMemcpyHostToDevice, plan->stream));
-  NLV_HIP(plan, hipStreamSynchronize(plan->stream));
+  NLV_HIP(plan, nlv::launch_compression_eig(plan->stream, plan->w.cov, plan->w.cov + (size_t)nlv::MAX_JP * nlv::MAX_JP,
+                                            J_phys, s.J, reinterpret_cast<float2*>(d_cc)));
   return NLINV_OK;
 }
 

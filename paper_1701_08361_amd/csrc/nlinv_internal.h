@@ -135,7 +135,7 @@ struct Bufs {
   int* kbq;       // [G*G] per-point fill cursors while a table is built
   float* kbc;     // [R] 1 / (sqrt(R) c(x)), deapodisation per axis
   float2* KG;     // [B][J][G][G] gridded samples
-  double2* cov;   // [MAX_JP][MAX_JP] channel covariance (compression calibration)
+  double2* cov;   // [2][MAX_JP][MAX_JP] channel covariance and its eigenvectors (compression calibration)
   double2* Vr;    // [B][J][GC][R] x-stage of W^-1 applied to the residual's coil block
   double2* Vp;    // [B][J][GC][R] the same for the CG direction (carried by linearity)
   double* pdfp;   // [B][NTB] Toeplitz-pass partials ||DF p||^2
@@ -233,5 +233,6 @@ hipError_t launch_kb_table(const Shape& s, const Bufs& w, hipStream_t st, const 
 constexpr int MAX_JP = 128;
 hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y);
 hipError_t launch_channel_cov(const Shape& s, hipStream_t st, const float2* y0, int Jp, double2* cov);
+hipError_t launch_compression_eig(hipStream_t st, double2* A, double2* V, int n, int J, float2* cc);
 
 }  // namespace nlv

@@ -512,6 +512,158 @@ hipError_t launch_channel_cov(const Shape& s, hipStream_t st, const float2* y0, 
   return hipGetLastError();
 }
 
+// Eigen-decomposition of the n x n Hermitian channel covariance by parallel
+// cyclic Jacobi rotations in one block (n <= MAX_JP): each element a_pq =
+// |a_pq| e^{i phi} is removed by U = diag(1, e^{-i phi}) R(theta), which
+// turns the 2 x 2 block real and rotates it diagonal (the classical Jacobi
+// method, Golub and Van Loan, Matrix Computations, Sec. 8.5, after the phase
+// change).  A sweep visits every pair once in n' - 1 rounds of n'/2 disjoint
+// pairs (n' = n rounded up to even; the round-robin order), and the rotations
+// of a round, which touch disjoint rows and columns, are applied together.
+// Sweeps stop when the off-diagonal mass is below 1e-30 of the diagonal's, or
+// after 100.  Then the rows of cc [J][n] are the conjugated eigenvectors of
+// the J largest eigenvalues, in descending order (ties: lower index first).
+constexpr int EIG_T = 1024;
+
+__global__ void __launch_bounds__(EIG_T)
+k_herm_jacobi(double2* __restrict__ A, double2* __restrict__ V, int n, int J, float2* __restrict__ cc) {
+  __shared__ double rot[MAX_JP / 2][6];     // per pair: c, s, e^{-i phi} (re, im), p, q
+  __shared__ double red[2][EIG_T / 64];
+  __shared__ int order[MAX_JP];
+  __shared__ int stop;
+  const int t = threadIdx.x;
+  const int m = n + (n & 1), half = m / 2;
+  for (int i = t; i < n * n; i += EIG_T) V[i] = make_double2((i / n) == (i % n) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int i = t; i < n * n; i += EIG_T) {
+      const int r = i / n, c = i % n;
+      const double v = A[i].x * A[i].x + A[i].y * A[i].y;
+      if (c > r) off += v;
+      if (c == r) dg += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_down(off, o, 64);
+      dg += __shfl_down(dg, o, 64);
+    }
+    if ((t & 63) == 0) {
+      red[0][t >> 6] = off;
+      red[1][t >> 6] = dg;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double so = 0.0, sd = 0.0;
+      for (int w = 0; w < EIG_T / 64; ++w) {
+        so += red[0][w];
+        sd += red[1][w];
+      }
+      stop = so <= 1e-30 * (sd + 1e-300);
+    }
+    __syncthreads();
+    if (stop) break;
+    for (int r = 0; r < m - 1; ++r) {
+      if (t < half) {
+        int p = t == 0 ? m - 1 : (r + t) % (m - 1);
+        int q = t == 0 ? r : (r - t + m - 1) % (m - 1);
+        if (p > q) {
+          const int u = p;
+          p = q;
+          q = u;
+        }
+        double c = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+        bool live = false;                        // a real pair with a nonzero element
+        if (q < n) {
+          const double2 apq = A[p * n + q];
+          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+          if (mag > 0.0) {
+            live = true;
+            er = apq.x / mag;                     // e^{-i phi} = conj(a_pq) / |a_pq|
+            ei = -apq.y / mag;
+            const double app = A[p * n + p].x, aqq = A[q * n + q].x;
+            const double tau = (aqq - app) / (2.0 * mag);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            sn = tt * c;
+          }
+        }
+        rot[t][0] = c;
+        rot[t][1] = sn;
+        rot[t][2] = er;
+        rot[t][3] = ei;
+        rot[t][4] = p;
+        rot[t][5] = live ? q : -1;
+      }
+      __syncthreads();
+      // A <- A U and V <- V U: columns p, q of every row k
+      for (int i = t; i < n * half; i += EIG_T) {
+        const int k = i / half, j = i % half;
+        const int q = (int)rot[j][5];
+        if (q < 0) continue;
+        const int p = (int)rot[j][4];
+        const double c = rot[j][0], sn = rot[j][1], er = rot[j][2], ei = rot[j][3];
+        // column p of U: (c, -s e^{-i phi}); column q: (s, c e^{-i phi})
+        const double2 upq = make_double2(-sn * er, -sn * ei), uqq = make_double2(c * er, c * ei);
+        for (int w = 0; w < 2; ++w) {
+          double2* M = w ? V : A;
+          const double2 akp = M[k * n + p], akq = M[k * n + q];
+          M[k * n + p] = make_double2(akp.x * c + akq.x * upq.x - akq.y * upq.y, akp.y * c + akq.x * upq.y + akq.y * upq.x);
+          M[k * n + q] = make_double2(akp.x * sn + akq.x * uqq.x - akq.y * uqq.y, akp.y * sn + akq.x * uqq.y + akq.y * uqq.x);
+        }
+      }
+      __syncthreads();
+      // A <- U^H A: rows p, q of every column k
+      for (int i = t; i < n * half; i += EIG_T) {
+        const int k = i / half, j = i % half;
+        const int q = (int)rot[j][5];
+        if (q < 0) continue;
+        const int p = (int)rot[j][4];
+        const double c = rot[j][0], sn = rot[j][1], er = rot[j][2], ei = rot[j][3];
+        // conj(U) entries: conj(-s e^{-i phi}), conj(c e^{-i phi})
+        const double2 cpq = make_double2(-sn * er, sn * ei), cqq = make_double2(c * er, -c * ei);
+        const double2 apk = A[p * n + k], aqk = A[q * n + k];
+        A[p * n + k] = make_double2(c * apk.x + cpq.x * aqk.x - cpq.y * aqk.y, c * apk.y + cpq.x * aqk.y + cpq.y * aqk.x);
+        A[q * n + k] = make_double2(sn * apk.x + cqq.x * aqk.x - cqq.y * aqk.y, sn * apk.y + cqq.x * aqk.y + cqq.y * aqk.x);
+      }
+      __syncthreads();
+      if (t < half) {
+        const int q = (int)rot[t][5];
+        if (q >= 0) {
+          const int p = (int)rot[t][4];
+          A[p * n + q] = make_double2(0.0, 0.0);
+          A[q * n + p] = make_double2(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) {
+    // the J largest eigenvalues, descending; ties keep the lower index first
+    unsigned long long used[(MAX_JP + 63) / 64] = {};
+    for (int j = 0; j < J; ++j) {
+      int best = -1;
+      for (int i = 0; i < n; ++i) {
+        if ((used[i >> 6] >> (i & 63)) & 1ull) continue;
+        if (best < 0 || A[i * n + i].x > A[best * n + best].x) best = i;
+      }
+      used[best >> 6] |= 1ull << (best & 63);
+      order[j] = best;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < J * n; i += EIG_T) {
+    const int j = i / n, p = i % n;
+    const double2 v = V[p * n + order[j]];
+    cc[i] = make_float2((float)v.x, (float)-v.y);
+  }
+}
+
+hipError_t launch_compression_eig(hipStream_t st, double2* A, double2* V, int n, int J, float2* cc) {
+  if (n < 1 || n > MAX_JP || J < 1 || J > n) return hipErrorInvalidValue;
+  k_herm_jacobi<<<1, EIG_T, 0, st>>>(A, V, n, J, cc);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const Shape& s, const Bufs& w, hipStream_t st, const double2* p,
                            double alpha, float2* out, bool image_block) {
   k_finalize<float2><<<s.B * s.NCH, VT, 0, st>>>(image_block ? w.PR : nullptr, p, alpha, w.Q, out, s.J,
