@@ -160,7 +160,7 @@ int nlinv_budget_used(int32_t device, size_t* used_bytes);
  * current).  The call allocates no device memory.
  *   - NLINV_E_WORKSPACE: the parameters need more workspace than the array
  *     holds (nlinv_workspace_size > NLINV_STATIC_WORKSPACE_BYTES; e.g. 160 px,
- *     10 coils, 5 turns, batch 1 needs 73 MiB and fits).
+ *     10 coils, 5 turns, batch 1 needs 81 MiB and fits).
  *   - NLINV_E_STATE: another plan on the static workspace of the current
  *     device is still alive (one at a time per GPU; destroy it first).
  * The array keeps the last plan's contents; a new plan rebuilds every table

@@ -2,11 +2,11 @@
 of the 160 px, 10-coil, 15-spoke real-time series (5 Newton steps of 20 CG
 iterations, alpha_0 = 1, Sobolev weight (880, 16)), the loss
 L = ||image - phantom||^2 on the combined image |rho| sqrt(sum_j |c_j|^2),
-sampled image pixels, and the derivatives of L along two seeded data
+sampled image pixels, and the derivatives of L along eight seeded data
 directions and in alpha_0, a and l, each by central differences of the
 oracle's reconstruction at two steps h and h/2, combined by Richardson
 extrapolation (the file also keeps both estimates and their relative spread).  It calls only the oracle and the
-seeded input generators.  Takes about half an hour on 8 cores:
+seeded input generators.  Takes about half an hour on 8 cores (45 oracle reconstructions):
 
     python tests/golden/make_unrolled160.py
 """
@@ -30,7 +30,7 @@ from oracle import nlinv_oracle as O  # noqa: E402
 from paper_1701_08361_amd import synth  # noqa: E402
 
 CASE = dict(seed=73, N=160, J=10, K=15, newton=5, cg=20, alpha0=1.0, a=880.0, l=16.0)
-DIRECTIONS = [1601, 1602]           # seeds of the data directions u_k (synth.random_samples)
+DIRECTIONS = list(range(1601, 1609))   # seeds of the data directions u_k (synth.random_samples)
 REL_STEP = {"alpha0": 1e-4, "a": 1e-4, "l": 1e-5, "y": 1e-4}
 N_PIXELS = 64
 

@@ -321,13 +321,17 @@ def test_unrolled_gradients_match_fp64(torch):
 GOLDEN_160 = os.path.join(os.path.dirname(__file__), "golden", "unrolled160.json")
 
 
-@pytest.mark.skip(reason="tolerance being derived from the FP64 sensitivity of the 5 x 20 iteration")
 def test_unrolled_160px_five_newton_against_oracle_differences(torch):
     """160 px, 10 coils, 15 spokes, 5 Newton x 20 CG in the Toeplitz form,
-    loss ||image - phantom||^2: the loss, sampled image pixels and the
-    derivatives along two data directions and in alpha_0, a and l against
-    the oracle's FP64 reconstruction and its central differences
-    (tests/golden/unrolled160.json, written by make_unrolled160.py)."""
+    loss ||image - phantom||^2: the loss, sampled image pixels, the
+    derivatives in alpha_0, a and l, and the data gradient's projections on
+    eight seeded directions against the oracle's FP64 reconstruction and its
+    central differences (tests/golden/unrolled160.json, written by
+    make_unrolled160.py).  The data gradient is judged by
+    sqrt(sum_k (g.u_k - d_k)^2 / sum_k d_k^2): for random directions both
+    sums estimate ||g - grad||^2 and ||grad||^2 up to the same factor, so the
+    ratio estimates the gradient's relative error; a single projection can
+    be small and make its own relative error large."""
     from paper_1701_08361_amd import autograd as AG
     from paper_1701_08361_amd import unrolled as UR
     with open(GOLDEN_160) as f:
@@ -351,15 +355,22 @@ def test_unrolled_160px_five_newton_against_oracle_differences(torch):
     e_pix = float(np.max(np.abs(im[idx] - np.asarray(gold["pixels"]["value"])))) / gold["image_norm"]
     e_norm = abs(float(np.linalg.norm(im)) - gold["image_norm"]) / gold["image_norm"]
     e_loss = abs(float(loss) - gold["loss"]) / gold["loss"]
-    gy = y.grad.cpu().numpy().astype(np.complex128)
+    ref = gold["derivatives"]
     got = {"alpha0": float(a0.grad), "a": float(a.grad), "l": float(l.grad)}
+    e = {k: abs(got[k] - ref[k]) / abs(ref[k]) for k in got}
+    gy = y.grad.cpu().numpy().astype(np.complex128)
+    num = den = 0.0
     for k, d in enumerate(gold["data_directions"]):
         u = synth.random_samples(d["seed"], J, s.y.shape[-1]).astype(np.complex128)
-        got[f"y.u{k}"] = float(np.real(np.vdot(gy[0], u)))
-    e = {k: abs(got[k] - gold["derivatives"][k]) / abs(gold["derivatives"][k]) for k in got}
+        gu = float(np.real(np.vdot(gy[0], u)))
+        num += (gu - ref[f"y.u{k}"]) ** 2
+        den += ref[f"y.u{k}"] ** 2
+        print(f"  y.u{k}: {gu:.6e} vs {ref[f'y.u{k}']:.6e}")
+    e["y"] = float(np.sqrt(num / den))
     print(f"loss {float(loss):.6e} vs {gold['loss']:.6e} (rel {e_loss:.2e}); image norm rel {e_norm:.2e}; "
           f"sampled pixels max rel {e_pix:.2e}; "
-          + "; ".join(f"{k} {got[k]:.6e} vs {gold['derivatives'][k]:.6e} (rel {e[k]:.2e})" for k in got))
+          + "; ".join(f"{k} {got[k]:.6e} vs {ref[k]:.6e}" for k in got)
+          + "; relative errors " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e_norm < 1e-4 and e_pix < 1e-4 and e_loss < 1e-3
     assert all(v < TOL_160 for v in e.values())
     plan.close()
