@@ -152,13 +152,14 @@ def compulsory_bytes_per_cg() -> float:
 
 
 def run_mode(torch, nl, data, B, steps, warmup, timer_kernels, kt_frames, graphs, img_store=None, flags=0,
-             cg_passes=0):
+             cg_passes=0, fft_split=0):
     """Advance B series by warmup + steps frames (timed), then kt_frames more
     per kernel class in `timer_kernels` with the class's launches timed by HIP
     events.  Returns per-step ms, total ms of the timed steps, and
     {class: (ms, launches)}.  img_store[n] (optional) receives the image of
     frame n of item 0."""
-    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=flags, col_tile=COL_TILE, cg_passes=cg_passes)
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, flags=flags, col_tile=COL_TILE, cg_passes=cg_passes,
+                   fft_split=fft_split)
     plan.set_graphs(graphs)
     import numpy as np
     traj = torch.from_numpy(np.stack([d[0] for d in data], axis=1)).cuda()  # [F,B,K,S_r,2]
@@ -507,7 +508,7 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
     for frames in frame_counts:
         frames = min(frames, traj_all.shape[0])
         p = dict(mode="single-slice", N=N, J=J, K=K, U=U, frames=frames, newton=M, cg=C)
-        tuner = AT.Autotuner(db, learning=True, tiles=(8, 4), passes=(6, 4))
+        tuner = AT.Autotuner(db, learning=True, tiles=(8, 4), passes=(6, 4), splits=(0, 1))
         if not graphs_allowed:
             tuner.space = [c for c in tuner.space if not c["graphs"]]
         tuner.learn(p, lambda c: AT.run_series(nl, torch, traj_all[:frames], y_all[:frames],
@@ -516,11 +517,13 @@ def run_autotune(torch, nl, data, frame_counts, graphs_allowed):
         (bc, bf), (wc, wf) = hits[0], hits[-1]
         rows.append({"frames": frames, "settings": len(hits),
                      "worst": dict(wc, fps=wf), "best": dict(bc, fps=bf),
-                     "all": [[c["T"], c["graphs"], c["col_tile"], c["cg_passes"], round(f, 1)] for c, f in hits]})
+                     "all": [[c["T"], c["graphs"], c["col_tile"], c["cg_passes"], c["fft_split"], round(f, 1)]
+                             for c, f in hits]})
     return {"form": "learning mode over T = 1..8 frames per relaxed group (l = 5 strict frames first), A = 1, "
                     "HIP graphs off/on, column-pass tile schedule 8 or 4 columns per block, CG iteration of 6 or 4 "
-                    "passes; rate = frames / wall time of the whole series (gridding + reconstruction); 'all' "
-                    "rows are [T, graphs, col_tile, cg_passes, fps]",
+                    "passes, Toeplitz-pass factorisation default or alternative; rate = frames / wall time of the "
+                    "whole series (gridding + reconstruction); 'all' rows are [T, graphs, col_tile, cg_passes, "
+                    "fft_split, fps]",
             "by_frames": rows}
 
 
@@ -776,6 +779,10 @@ def main():
                     help="CG iteration form of the batch-1 plans (4: folded, measured faster at batch 1)")
     ap.add_argument("--cg-passes-batched", type=int, default=6, choices=[0, 4, 6],
                     help="CG iteration form of the batched plans (6: fewer bytes, measured faster at batch 16)")
+    ap.add_argument("--fft-split-plain", type=int, default=0, choices=[0, 1],
+                    help="factorisation of the Toeplitz row pass in the batch-1 plans (0: the grid's default)")
+    ap.add_argument("--fft-split-batched", type=int, default=0, choices=[0, 1],
+                    help="factorisation of the Toeplitz row pass in the batched plans")
     ap.add_argument("--grid-lut-reps", type=int, default=0,
                     help="applications timed per grid side for the grid-size lookup table (0 = skip)")
     args = ap.parse_args()
@@ -851,7 +858,8 @@ def main():
         img_strict = torch.zeros((max(args.warmup, 2 * U) if args.graphs else args.warmup) + args.steps, N, N,
                                  dtype=torch.float32, device="cuda")
         per, total, kt = run_mode(torch, nl, plain_data, 1, args.steps, args.warmup, KT_CLASSES, args.kt_frames,
-                                  args.graphs, img_store=img_strict, flags=flags, cg_passes=args.cg_passes_plain)
+                                  args.graphs, img_store=img_strict, flags=flags, cg_passes=args.cg_passes_plain,
+                                  fft_split=args.fft_split_plain)
         fps = args.steps / (total / 1e3)
         out.update({"value": fps, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps,
                     "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)},
@@ -872,7 +880,8 @@ def main():
     if batch_data is not None:
         B = args.batch
         per, total, kt = run_mode(torch, nl, batch_data, B, args.batch_steps, args.warmup, KT_CLASSES,
-                                  args.kt_frames, args.graphs, flags=flags, cg_passes=args.cg_passes_batched)
+                                  args.kt_frames, args.graphs, flags=flags, cg_passes=args.cg_passes_batched,
+                                  fft_split=args.fft_split_batched)
         out["batched"] = {"batch": B, "steps": args.batch_steps, "fps": B * args.batch_steps / (total / 1e3),
                           "ms_per_step": total / args.batch_steps,
                           "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99), "min": min(per)},
@@ -888,7 +897,7 @@ def main():
         hb = args.hbm_batch
         data_hb = [batch_data[i % len(batch_data)] for i in range(hb)]
         _, total_hb, kt = run_mode(torch, nl, data_hb, hb, 2, 0, KT_CLASSES, 1, args.graphs, flags=flags,
-                                   cg_passes=args.cg_passes_batched)
+                                   cg_passes=args.cg_passes_batched, fft_split=args.fft_split_batched)
         kt_by_batch[hb] = kt
         out["hbm_check"] = {"batch": hb, "fps": hb * 2 / (total_hb / 1e3)}
     if batch_data is not None and args.serve_slices > 0:
@@ -944,6 +953,7 @@ def main():
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
                      "plain_batch": 1, "batched_batch": args.batch, "cg_passes_plain": args.cg_passes_plain,
                      "cg_passes_batched": args.cg_passes_batched,
+                     "fft_split_plain": args.fft_split_plain, "fft_split_batched": args.fft_split_batched,
                      "hip_graphs": args.graphs,
                      "data_gen_s": round(t_gen, 1)}
     if kt_by_batch:

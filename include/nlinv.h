@@ -115,6 +115,12 @@ typedef struct {
                       /* kernels fewer, about 15 % more bytes); 0 (default) =  */
                       /* 6.  Both forms are the same CG in exact arithmetic;   */
                       /* they differ in rounding only                          */
+  int32_t fft_split;  /* factorisation G = G1 G2 of the Toeplitz row pass's  */
+                      /* team transforms: 0 (default) the grid's own (G1 = 16 */
+                      /* for G >= 128), 1 an alternative (the swapped order,  */
+                      /* e.g. 20 x 16 at G = 320; 32 x 8 at 256, 16 x 4 at   */
+                      /* 64).  The same transform in exact arithmetic; the    */
+                      /* faster one is a measurement (autotuner dimension)    */
 } nlinv_params;
 
 /* Fill `p` with the defaults above (N, K left 0).  Never fails for non-NULL p. */

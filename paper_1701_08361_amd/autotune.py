@@ -25,7 +25,9 @@ A tuner may also search the tile schedule of the CG column passes
 (col_tile: columns per block, 8 or 4; the same images bit for bit) and the
 pass fusion of a CG iteration (cg_passes: six dependent kernels, or four with
 the direction update, the coil rows of the direction and the vector step
-folded into the operator's passes; the same images to rounding), so that the
+folded into the operator's passes; the same images to rounding) and the
+factorisation G = G1 G2 of the Toeplitz row pass's transforms (fft_split: the
+grid's default or its alternative; the same images to rounding), so that the
 kernel decomposition is measured per protocol instead of fixed.
 
 The database is a JSON file (a list of records); the runner reconstructs a
@@ -52,16 +54,19 @@ def _norm_protocol(p: Dict) -> Dict:
 
 
 def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] = None,
-                 passes: Optional[Sequence[int]] = None) -> List[Dict]:
+                 passes: Optional[Sequence[int]] = None, splits: Optional[Sequence[int]] = None) -> List[Dict]:
     """Settings (T, A, graphs): for A = 1, T = 1..max_T; for A = 2 up to
     max_T / 2; for A = 3, 4 up to max_T / 4 (the paper's limits on 8 GPUs),
     with A <= gpus; each with graphs off and on; with `tiles`, each also with
     every listed column-pass tile schedule (col_tile); with `passes`, each
-    also with every listed CG pass fusion (cg_passes, 4 or 6)."""
+    also with every listed CG pass fusion (cg_passes, 4 or 6); with `splits`,
+    each also with every listed Toeplitz-pass factorisation (fft_split, 0 or 1)."""
     if tiles is not None and (not tiles or any(t not in (4, 8) for t in tiles)):
         raise ValueError("tile schedules are 4 or 8 columns per block")
     if passes is not None and (not passes or any(p not in (4, 6) for p in passes)):
         raise ValueError("a CG iteration has 4 or 6 passes")
+    if splits is not None and (not splits or any(f not in (0, 1) for f in splits)):
+        raise ValueError("factorisations are 0 (the grid's default) and 1 (its alternative)")
     out = []
     for A in (1, 2, 3, 4):
         if A > gpus:
@@ -74,6 +79,8 @@ def search_space(gpus: int = 1, max_T: int = 8, tiles: Optional[Sequence[int]] =
                     base = [dict(c, col_tile=int(t)) for c in base for t in tiles]
                 if passes is not None:
                     base = [dict(c, cg_passes=int(p)) for c in base for p in passes]
+                if splits is not None:
+                    base = [dict(c, fft_split=int(f)) for c in base for f in splits]
                 out.extend(base)
     return out
 
@@ -134,9 +141,10 @@ def protocol_distance(a: Dict, b: Dict) -> float:
 
 class Autotuner:
     def __init__(self, db: TuningDB, gpus: int = 1, max_T: int = 8, learning: bool = False,
-                 tiles: Optional[Sequence[int]] = None, passes: Optional[Sequence[int]] = None):
+                 tiles: Optional[Sequence[int]] = None, passes: Optional[Sequence[int]] = None,
+                 splits: Optional[Sequence[int]] = None):
         self.db, self.learning = db, learning
-        self.space = search_space(gpus, max_T, tiles, passes)
+        self.space = search_space(gpus, max_T, tiles, passes, splits)
 
     def untried(self, protocol: Dict) -> List[Dict]:
         tried = [c for c, _ in self.db.lookup(protocol)]
@@ -189,7 +197,7 @@ def run_series(nl, torch, traj, y, turns, config: Dict, newton: int, cg: int, U:
     K = traj.shape[1]
     l = U if l is None else l
     plan = nl.Plan(N, J, K, U=U, batch=T, newton=newton, cg=cg, col_tile=int(config.get("col_tile", 0)),
-                   cg_passes=int(config.get("cg_passes", 0)))
+                   cg_passes=int(config.get("cg_passes", 0)), fft_split=int(config.get("fft_split", 0)))
     try:
         plan.set_graphs(bool(config.get("graphs", True)))
         for t in range(min(U, F)):

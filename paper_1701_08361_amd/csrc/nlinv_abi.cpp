@@ -130,6 +130,7 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
     return bad(NLINV_E_ARG, "Sobolev parameters must be finite and >= 0");
   if (p->col_tile != 0 && p->col_tile != 4 && p->col_tile != 8) return bad(NLINV_E_ARG, "col_tile must be 0, 4 or 8");
   if (p->cg_passes != 0 && p->cg_passes != 4 && p->cg_passes != 6) return bad(NLINV_E_ARG, "cg_passes must be 0, 4 or 6");
+  if (p->fft_split != 0 && p->fft_split != 1) return bad(NLINV_E_ARG, "fft_split must be 0 or 1");
 
   Shape& S = *s;
   S.B = p->batch;
@@ -153,7 +154,9 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   S.stride = st;
   S.coltile = p->col_tile;
   S.gsplit = nlv::grid_nsplit(S.B, S.J, S.R);
-  S.NTB = (S.J * S.G + tab->row_lines - 1) / tab->row_lines;
+  S.split = p->fft_split;
+  const int trl = S.split ? tab->row_lines_split : tab->row_lines;   // lines per Toeplitz-pass block
+  S.NTB = (S.J * S.G + trl - 1) / trl;
   S.NPP = S.J * S.R;
   // Kaiser-Bessel gridding tables: (W + 1)^2 entries per sample and turn; left
   // out (exact gridding only) when they would take more than 2 GiB

@@ -272,22 +272,39 @@ struct DFT<7, DIR, C> {
 // team four-step transforms
 // ---------------------------------------------------------------------------
 
-template <int G>
-struct FS;
-template <> struct FS<64>  { static constexpr int G1 = 8,  G2 = 8;  };
-template <> struct FS<128> { static constexpr int G1 = 16, G2 = 8;  };
-template <> struct FS<256> { static constexpr int G1 = 16, G2 = 16; };
-template <> struct FS<320> { static constexpr int G1 = 16, G2 = 20; };
-template <> struct FS<384> { static constexpr int G1 = 16, G2 = 24; };
-template <> struct FS<432> { static constexpr int G1 = 16, G2 = 27; };
-template <> struct FS<448> { static constexpr int G1 = 16, G2 = 28; };
-template <> struct FS<480> { static constexpr int G1 = 16, G2 = 30; };
-template <> struct FS<512> { static constexpr int G1 = 16, G2 = 32; };
+// The factorisation G = G1 G2 of a grid's team transform.  A team key
+// names a grid side and one of its factorisations: key = G + split * GKEY,
+// split 0 the default below, split 1 an alternative (the swapped order
+// G2 G1, or for a square split another one); every kernel that takes a key
+// derives the grid side with grid_of.
+constexpr int GKEY = 1 << 16;
+constexpr int grid_of(int key) { return key % GKEY; }
 
 template <int G>
+struct FS0;
+template <> struct FS0<64>  { static constexpr int G1 = 8,  G2 = 8,  A1 = 16, A2 = 4;  };
+template <> struct FS0<128> { static constexpr int G1 = 16, G2 = 8,  A1 = 8,  A2 = 16; };
+template <> struct FS0<256> { static constexpr int G1 = 16, G2 = 16, A1 = 32, A2 = 8;  };
+template <> struct FS0<320> { static constexpr int G1 = 16, G2 = 20, A1 = 20, A2 = 16; };
+template <> struct FS0<384> { static constexpr int G1 = 16, G2 = 24, A1 = 24, A2 = 16; };
+template <> struct FS0<432> { static constexpr int G1 = 16, G2 = 27, A1 = 27, A2 = 16; };
+template <> struct FS0<448> { static constexpr int G1 = 16, G2 = 28, A1 = 28, A2 = 16; };
+template <> struct FS0<480> { static constexpr int G1 = 16, G2 = 30, A1 = 30, A2 = 16; };
+template <> struct FS0<512> { static constexpr int G1 = 16, G2 = 32, A1 = 32, A2 = 16; };
+
+template <int KEY>
+struct FS {
+  static constexpr int G = grid_of(KEY), split = KEY / GKEY;
+  static_assert(split == 0 || split == 1, "bad team key");
+  static constexpr int G1 = split ? FS0<G>::A1 : FS0<G>::G1;
+  static constexpr int G2 = split ? FS0<G>::A2 : FS0<G>::G2;
+};
+
+template <int KEY>
 struct Team {
-  static constexpr int G1 = FS<G>::G1, G2 = FS<G>::G2;
-  static_assert(G1 * G2 == G, "bad factorisation");
+  static constexpr int GRID = grid_of(KEY);
+  static constexpr int G1 = FS<KEY>::G1, G2 = FS<KEY>::G2;
+  static_assert(G1 * G2 == GRID, "bad factorisation");
   static constexpr int SIZE = G1 > G2 ? G1 : G2;   // threads per line
   static constexpr int LDSN = G1 * (G2 + 1);       // complex LDS slots per line (padded)
   // Line pitch of the column passes, whose neighbouring lanes work on
@@ -313,10 +330,10 @@ constexpr int classify(int G, int set, int lo, int len) {
 }
 // index n = tl + G1 * N2 (tl in [0, G1)): fsA inputs, fsB outputs
 template <int G, int SET, int N2>
-constexpr int cls_n() { return classify(G, SET, Team<G>::G1 * N2, Team<G>::G1); }
+constexpr int cls_n() { return classify(Team<G>::GRID, SET, Team<G>::G1 * N2, Team<G>::G1); }
 // index k = G2 * K1 + tl (tl in [0, G2)): fsA outputs, fsB inputs
 template <int G, int SET, int K1>
-constexpr int cls_k() { return classify(G, SET, Team<G>::G2 * K1, Team<G>::G2); }
+constexpr int cls_k() { return classify(Team<G>::GRID, SET, Team<G>::G2 * K1, Team<G>::G2); }
 
 // runtime twiddle exp(DIR i 2 pi m / G) from the host-built FP64 table tw[m] = (cos, sin)
 template <int DIR, class C>

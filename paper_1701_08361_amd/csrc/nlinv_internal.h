@@ -85,6 +85,7 @@ struct Shape {
   int coltile;         // tile schedule of cols_fwd / cols_back: 0 (the library's), 4 or 8
   int NTB;             // Toeplitz-pass blocks per item of the four-pass CG (ceil(J G / row_lines))
   int NPP;             // direction-partial slots per item (J * R: one per channel and column)
+  int split;           // factorisation of the Toeplitz row pass: 0 the grid's default, 1 its alternative
 };
 
 // Columns per block of a CG column pass (the plan's tile schedule; the
@@ -202,6 +203,7 @@ struct GTable {
   hipError_t (*kb_grid)(const Shape&, const Bufs&, hipStream_t, const TurnArgs& turns, const float2* y,
                         float2* z);
   int row_lines;   // lines per block of the coil row passes
+  int row_lines_split;   // lines per block of the Toeplitz row pass under the alternative factorisation
 };
 
 // Table for grid size G, or nullptr if unsupported.

@@ -398,13 +398,15 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 // item's J G lines, the last one partial) and each block also writes the
 // partial sum_k P(k) |U(k)|^2 of its lines' spectra to part[b * pstride +
 // block]: summed over an item it is <u, F^H F u> = ||DF p||^2 (Parseval), the
-// operator part of Re<p, q> in the four-pass CG iteration.
-template <int G, class S2, bool PQ = false>
-__global__ void __launch_bounds__(row_threads<G>())
+// operator part of Re<p, q> in the four-pass CG iteration.  KEY names the
+// grid side and the factorisation of its team transform (nlinv_fft.h), so
+// that the factorisation of this pass can be chosen per plan.
+template <int KEY, class S2, bool PQ = false>
+__global__ void __launch_bounds__(row_threads<KEY>())
 k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
             const double2* __restrict__ tw, int J, int nlines, double* __restrict__ part, int pstride, int nbi) {
-  using T = Team<G>;
-  constexpr int R = G / 2, RT = row_lines<G>();
+  using T = Team<KEY>;
+  constexpr int G = grid_of(KEY), R = G / 2, RT = row_lines<KEY>();
   __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[64];
   const int rl0 = (int)threadIdx.x / T::SIZE;
@@ -432,7 +434,7 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
     });
   }
   C v[T::G1];
-  fsA<G, -1, SET_IMG, SET_ALL>(tl, L, tw, [&](int n) -> C {
+  fsA<KEY, -1, SET_IMG, SET_ALL>(tl, L, tw, [&](int n) -> C {
     const int ix = img_idx<G>(n);
     return ix < 0 ? czero<C>() : to_d(nt_load(line + ix));
   }, v);
@@ -445,11 +447,11 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
     });
   }
   if constexpr (PQ) {
-    static_assert(row_threads<G>() == 64, "one wavefront per block");
+    static_assert(row_threads<KEY>() == 64, "one wavefront per block");
     const double s = block_sum_waves<64>(acc, sh);
     if (threadIdx.x == 0) part[(size_t)(blockIdx.x / nbi) * pstride + blockIdx.x % nbi] = s;
   }
-  fsB<G, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
+  fsB<KEY, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
     const int ix = img_idx<G>(n);
     if (ix >= 0) nt_store(line + ix, store_as<S2>(val));
   });
@@ -1167,17 +1169,17 @@ struct GLaunch {
                              const float2* xh, const double2* pv, void* out) {
     return cols_fwd_t<double2>(s, w, st, mode, co, xh, pv, out);
   }
-  template <class S2>
+  template <class S2, int KEY>
   static hipError_t toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    constexpr int RT = row_lines<G>();
+    constexpr int RT = row_lines<KEY>();
     const int nlines = s.B * s.J * s.G;
     const int blocks = (nlines + RT - 1) / RT;
-    return launch_timed(w, k_toep_rows<G, S2, false>, dim3(blocks), dim3(row_threads<G>()), 0, st,
+    return launch_timed(w, k_toep_rows<KEY, S2, false>, dim3(blocks), dim3(row_threads<KEY>()), 0, st,
                         static_cast<S2*>(w.U2), (const float*)w.P, turns, (const double2*)w.tw, s.J, nlines,
                         (double*)nullptr, 0, 1);
   }
   static hipError_t toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    return toep_rows_t<double2>(s, w, st, turns);
+    return s.split ? toep_rows_t<double2, G + GKEY>(s, w, st, turns) : toep_rows_t<double2, G>(s, w, st, turns);
   }
   template <class S2, int TWC>
   static hipError_t cols_back_k(const Shape& s, const Bufs& w, hipStream_t st, int mode, const void* in,
@@ -1250,14 +1252,17 @@ struct GLaunch {
                                 const double2* pold, double2* pnew, Partials sc, int first) {
     return cg_cols_fwd_t<double2>(s, w, st, xh, pold, pnew, sc, first);
   }
-  template <class S2>
+  // s.NTB blocks per item: the plan's derivation sizes it with the row
+  // lines of the chosen factorisation (GTable::row_lines_split)
+  template <class S2, int KEY>
   static hipError_t cg_toep_rows_t(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    return launch_timed(w, k_toep_rows<G, S2, true>, dim3(s.B * s.NTB), dim3(row_threads<G>()), 0, st,
+    return launch_timed(w, k_toep_rows<KEY, S2, true>, dim3(s.B * s.NTB), dim3(row_threads<KEY>()), 0, st,
                         static_cast<S2*>(w.U2), (const float*)w.P, turns, (const double2*)w.tw, s.J,
                         s.B * s.J * s.G, w.pdfp, s.NTB, s.NTB);
   }
   static hipError_t cg_toep_rows(const Shape& s, const Bufs& w, hipStream_t st, const TurnArgs& turns) {
-    return cg_toep_rows_t<double2>(s, w, st, turns);
+    return s.split ? cg_toep_rows_t<double2, G + GKEY>(s, w, st, turns)
+                   : cg_toep_rows_t<double2, G>(s, w, st, turns);
   }
   template <class S2, int TWC>
   static hipError_t cg_cols_back_k(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
@@ -1326,7 +1331,8 @@ constexpr GTable make_table() {
   return GTable{&GLaunch<G>::coil_rows, &GLaunch<G>::coil_rows_cg, &GLaunch<G>::cols_fwd,
                 &GLaunch<G>::toep_rows, &GLaunch<G>::cols_back, &GLaunch<G>::coilh_rows,
                 &GLaunch<G>::cg_cols_fwd, &GLaunch<G>::cg_toep_rows, &GLaunch<G>::cg_cols_back,
-                &GLaunch<G>::cg_coilh, &GLaunch<G>::psf_fft, &GLaunch<G>::kb_grid, row_lines<G>()};
+                &GLaunch<G>::cg_coilh, &GLaunch<G>::psf_fft, &GLaunch<G>::kb_grid, row_lines<G>(),
+                row_lines<G + GKEY>()};
 }
 
 }  // namespace nlv

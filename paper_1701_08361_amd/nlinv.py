@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("newton", ctypes.c_int32), ("cg", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("alpha0", ctypes.c_double), ("alpha_q", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("sob_a", ctypes.c_double), ("sob_l", ctypes.c_double),
-                ("col_tile", ctypes.c_int32), ("cg_passes", ctypes.c_int32)]
+                ("col_tile", ctypes.c_int32), ("cg_passes", ctypes.c_int32), ("fft_split", ctypes.c_int32)]
 
 
 _lib = None
@@ -115,7 +115,7 @@ def _check(rc: int, plan=None):
 def make_params(N: int, J: int, K: int, S_r: int = 0, U: int = 1, batch: int = 1, newton: int = 7,
                 cg: int = 10, alpha0: float = 1.0, alpha_q: float = 0.5, alpha_min: float = 0.0,
                 G: int = 0, sob_a: float = 880.0, sob_l: float = 16.0, flags: int = 0,
-                col_tile: int = 0, cg_passes: int = 0) -> Params:
+                col_tile: int = 0, cg_passes: int = 0, fft_split: int = 0) -> Params:
     p = Params()
     _check(load().nlinv_params_default(ctypes.byref(p)))
     p.N, p.G, p.J, p.K, p.S_r, p.U, p.batch = N, G, J, K, S_r, U, batch
@@ -123,6 +123,7 @@ def make_params(N: int, J: int, K: int, S_r: int = 0, U: int = 1, batch: int = 1
     p.alpha0, p.alpha_q, p.alpha_min, p.sob_a, p.sob_l = alpha0, alpha_q, alpha_min, sob_a, sob_l
     p.col_tile = col_tile
     p.cg_passes = cg_passes
+    p.fft_split = fft_split
     return p
 
 

@@ -60,6 +60,8 @@ def test_workspace_grows_with_batch(lib):
     (dict(N=64, J=8, K=13, alpha_min=-1.0), nl.E_ARG),
     (dict(N=0, J=8, K=13), nl.E_ARG),
     (dict(N=64, J=8, K=13, col_tile=2), nl.E_ARG),   # tile schedule: 0, 4 or 8
+    (dict(N=64, J=8, K=13, cg_passes=5), nl.E_ARG),  # a CG iteration has 4 or 6 passes
+    (dict(N=64, J=8, K=13, fft_split=2), nl.E_ARG),  # factorisations 0 and 1
 ])
 def test_invalid_params_rejected(lib, kw, code):
     p = nl.make_params(**kw)

@@ -106,3 +106,13 @@ def test_search_space_with_pass_fusion():
     tuner = AT.Autotuner(AT.TuningDB(), learning=True, tiles=(8, 4), passes=(6, 4))
     best = tuner.learn(proto(), rate)
     assert best == {"T": 3, "A": 1, "graphs": True, "col_tile": 4, "cg_passes": 4}
+
+
+def test_search_space_with_factorisation():
+    sp = AT.search_space(1, passes=(6, 4), splits=(0, 1))
+    assert len(sp) == 64 and {c["fft_split"] for c in sp} == {0, 1}
+    with pytest.raises(ValueError):
+        AT.search_space(1, splits=(2,))
+    rate = lambda c: fake_rate(c) + (0.3 if c["fft_split"] == 1 else 0.0)
+    tuner = AT.Autotuner(AT.TuningDB(), learning=True, splits=(0, 1))
+    assert tuner.learn(proto(), rate) == {"T": 3, "A": 1, "graphs": True, "fft_split": 1}

@@ -116,3 +116,33 @@ def test_cg_forms_match_oracle(torch, N, J, K, B, seed):
         d = rel(imgs[(4, 0)][b], imgs[(6, 0)][b])
         print(f"item {b}: six-pass rel {e6:.2e}, four-pass rel {e4:.2e}, between forms {d:.2e}")
         assert e6 < 1e-3 and e4 < 1e-3 and d < 1e-4
+
+
+@pytest.mark.parametrize("N,J,K,G", [(32, 2, 5, 0), (64, 4, 9, 0), (128, 3, 9, 0), (160, 4, 9, 0), (192, 3, 9, 0),
+                                     (216, 2, 9, 0), (224, 2, 9, 0), (240, 2, 9, 0), (256, 2, 9, 0)])
+def test_toeplitz_factorisations_match_oracle(torch, N, J, K, G):
+    """The alternative factorisation of the Toeplitz row pass (fft_split = 1;
+    every grid side): the CG operator against the oracle at the operator bar,
+    and a short reconstruction in both CG forms against the oracle at the
+    image bar."""
+    from paper_1701_08361_amd import nlinv as nl
+    print(f"[case] fft split N={N} J={J} K={K}", flush=True)
+    s = synth.single_frame(seed=41, N=N, J=J, K=K)
+    traj = torch.from_numpy(s.traj).cuda()
+    y = torch.from_numpy(s.y).cuda()
+    g = O.Geometry.make(N, J)
+    P = O.psf_kernel(s.traj[0], g.R, g.G)
+    x0 = synth.random_xhat(42, g.R, J, g.Gc, 1.0, 0.3)
+    p = synth.random_xhat(43, g.R, J, g.Gc, 1.0, 0.3)
+    ref_q = O.normal(g, x0.astype(np.complex128), p.astype(np.complex128), P) + 0.2 * p
+    xr = O.reconstruct(g, O.grid(s.y[0], s.traj[0], g.R), P, newton=2, cg_iters=4)
+    for passes in (6, 4):
+        plan = nl.Plan(N, J, K, newton=2, cg=4, fft_split=1, cg_passes=passes)
+        z = plan.grid(traj, y, turns=[0])
+        q = plan.apply_normal([0], torch.from_numpy(x0[None]).cuda(), torch.from_numpy(p[None]).cuda(), 0.2)
+        x, img, _ = plan.reconstruct(z, [0], want_img=True)
+        e_q = rel(q.cpu().numpy()[0], ref_q)
+        e_i = rel(img.cpu().numpy()[0], O.image(g, xr))
+        print(f"fft_split 1, {passes} passes: operator rel {e_q:.2e}, image rel {e_i:.2e}")
+        assert e_q < 1e-4 and e_i < 1e-3
+        plan.close()
