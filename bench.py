@@ -396,6 +396,53 @@ def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
     return per
 
 
+def run_ragged_operator(torch, nl, batches=None, reps=30, warmup=5):
+    """The CG operator of the three mixed shapes (one batched plan each, grids
+    256, 320, 384; `batches` items each, default the mixed run's 5 / 6 / 5)
+    applied with one ragged Toeplitz launch (nlinv_apply_normal_multi)
+    against one nlinv_apply_normal per plan, all on one stream; ms per
+    application of all three, host clock around synchronised GPU work."""
+    import numpy as np
+    from paper_1701_08361_amd import synth
+    plans, xs, ps, turns = [], [], [], []
+    shapes = [(n, j, k, b if batches is None else batches[i]) for i, (n, j, k, b) in enumerate(MIXED)]
+    for i, (n, j, k, b) in enumerate(shapes):
+        plan = nl.Plan(n, j, k, U=b, batch=b)
+        for t in range(b):
+            plan.psf(torch.from_numpy(synth.radial_trajectory(n, k, 2 * n, t, b)).cuda(), t)
+        xs.append(torch.from_numpy(np.stack([synth.random_xhat(300 + 10 * i + t, plan.R, j, plan.Gc, 1.0, 0.3)
+                                             for t in range(b)])).cuda())
+        ps.append(torch.from_numpy(np.stack([synth.random_xhat(400 + 10 * i + t, plan.R, j, plan.Gc, 1.0, 0.3)
+                                             for t in range(b)])).cuda())
+        plans.append(plan)
+        turns.append(list(range(b)))
+    qs = [pl.empty(pl.B, pl.X) for pl in plans]
+
+    def per_plan():
+        for pl, t, x, p, q in zip(plans, turns, xs, ps, qs):
+            pl.apply_normal(t, x, p, 0.1, q=q)
+
+    def ragged():
+        nl.apply_normal_multi(plans, turns, xs, [0.1] * len(plans), ps, qs)
+
+    res = {}
+    for name, fn in (("per_plan", per_plan), ("ragged", ragged), ("per_plan_again", per_plan),
+                     ("ragged_again", ragged)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / reps * 1e3
+    for pl in plans:
+        pl.close()
+    return {"batches": [b for (_, _, _, b) in shapes],
+            "per_plan_ms": min(res["per_plan"], res["per_plan_again"]),
+            "ragged_ms": min(res["ragged"], res["ragged_again"])}
+
+
 def run_mixed_one_launch(torch, nl, groups, steps, warmup, graphs):
     """The same series in ONE batched plan on the largest shape's grid: every
     item of a smaller image side runs at gamma = G / (2 N) on that grid, its
@@ -948,6 +995,12 @@ def main():
                                "ms_per_step": {"p50": pct(per, 50), "p99": pct(per, 99)},
                                "form": "all series in one batched plan on the largest grid (smaller image "
                                        "sides at gamma = G / 2N, zero channels, packed samples)"}
+        mixed["ragged_operator"] = {
+            "form": "CG operator of the 3 mixed shapes (grids 256 / 320 / 384) on one stream: one "
+                    "nlinv_apply_normal per plan, or nlinv_apply_normal_multi with one ragged persistent Toeplitz "
+                    "launch (the tiles of every shape in one list, each shape on its own grid); ms per "
+                    "application of all three",
+            "runs": [run_ragged_operator(torch, nl), run_ragged_operator(torch, nl, batches=(1, 1, 1))]}
         out["mixed"] = mixed
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",

@@ -286,6 +286,23 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
                        double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
 
+/* The CG operator of several plans of different grid sides in one go (the
+ * same result as nlinv_apply_normal per plan, bit for bit): every plan's
+ * passes run on plans[0]'s stream, and the Toeplitz row passes of all of
+ * them are one persistent launch whose blocks work through one list of
+ * tiles of every shape, each shape on its own grid (mixed image sides
+ * without padding to one grid).
+ *   count        1..3 plans, of grid sides 256, 320 and 384, at most one each
+ *                (NLINV_E_SIZE for other sides), default factorisation,
+ *                all on one device; their pending work on other streams must
+ *                be ordered before this call by the caller
+ *   h_turns[i]   host [B_i] turns of plan i; d_xhat[i], d_p[i], d_q[i] its
+ *                [B_i][X_i] point, direction and output (complex64);
+ *                alpha[i] host, finite */
+int nlinv_apply_normal_multi(int32_t count, const nlinv_plan* plans, const int32_t* const* h_turns,
+                             const nlinv_c64* const* d_xhat, const double* alpha, const nlinv_c64* const* d_p,
+                             nlinv_c64* const* d_q);
+
 /* The pieces of the IRGNM (Sec. 2.2) in the PSF-convolution form, for the
  * differentiable unrolled reconstruction.  E_x is the image-space part of the
  * derivative, DF_x = F E_x with E_x(p)_j = c_j d_rho + rho W^-1 d_c_hat_j

@@ -1060,6 +1060,73 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
   return NLINV_OK;
 }
 
+int nlinv_apply_normal_multi(int32_t count, const nlinv_plan* plans, const int32_t* const* h_turns,
+                             const nlinv_c64* const* d_xhat, const double* alpha, const nlinv_c64* const* d_p,
+                             nlinv_c64* const* d_q) {
+  if (count < 1 || count > 3) return fail(nullptr, NLINV_E_ARG, "count must be in [1, 3]");
+  if (!plans || !h_turns || !d_xhat || !alpha || !d_p || !d_q) return fail(nullptr, NLINV_E_ARG, "NULL array");
+  int slot_of[3] = {-1, -1, -1};   // plan index per ragged slot (grid 256, 320, 384)
+  nlv::TurnArgs turns[3];
+  for (int i = 0; i < count; ++i) {
+    nlinv_plan plan = plans[i];
+    NLV_CHECK(check_plan(plan));
+    NLV_CHECK(check_ptr(plan, d_xhat[i], "d_xhat"));
+    NLV_CHECK(check_ptr(plan, d_p[i], "d_p"));
+    NLV_CHECK(check_ptr(plan, d_q[i], "d_q"));
+    if (!std::isfinite(alpha[i])) return fail(plan, NLINV_E_ARG, "alpha must be finite");
+    if ((const void*)d_p[i] == (const void*)d_q[i]) return fail(plan, NLINV_E_ARG, "d_q must not alias d_p");
+    if (plan->device != plans[0]->device) return fail(plan, NLINV_E_ARG, "the plans must live on one device");
+    const int G = plan->s.G;
+    const int slot = G == 256 ? 0 : (G == 320 ? 1 : (G == 384 ? 2 : -1));
+    if (slot < 0) return fail(plan, NLINV_E_SIZE, "the ragged pass takes grids 256, 320 and 384");
+    if (slot_of[slot] >= 0) return fail(plan, NLINV_E_ARG, "one plan per grid side");
+    if (plan->s.split != 0) return fail(plan, NLINV_E_ARG, "the ragged pass uses the default factorisation");
+    slot_of[slot] = i;
+    NLV_CHECK(turns_of(plan, h_turns[i], &turns[i]));
+  }
+  hipStream_t st = plans[0]->stream;
+  nlinv_plan first = plans[0];
+  const Partials none{};
+  // every plan's passes on the first plan's stream
+  struct StreamSwap {
+    nlinv_plan p;
+    hipStream_t keep;
+    ~StreamSwap() { p->stream = keep; }
+  };
+  for (int i = 0; i < count; ++i) {
+    nlinv_plan plan = plans[i];
+    StreamSwap sw{plan, plan->stream};
+    plan->stream = st;
+    const Shape& s = plan->s;
+    Bufs& w = plan->w;
+    const float2* xh = reinterpret_cast<const float2*>(d_xhat[i]);
+    NLV_CHECK(coils_into(plan, xh, w.CO));
+    NLV_HIP(plan, nlv::launch_to_double(s, st, w.Pv[0], reinterpret_cast<const float2*>(d_p[i])));
+    NLV_HIP(plan, plan->t->coil_rows_cg(s, w, st, w.Pv[0], nullptr, nullptr, none));
+    NLV_HIP(plan, plan->t->cols_fwd(s, w, st, 1, w.CO, xh, w.Pv[0], w.U2));
+  }
+  nlv::ToepShape shapes[3];
+  for (int k = 0; k < 3; ++k) {
+    shapes[k] = nlv::ToepShape{nullptr, nullptr, nullptr, nlv::TurnArgs{}, 1, 0};
+    const int i = slot_of[k];
+    if (i < 0) continue;
+    const Shape& s = plans[i]->s;
+    const Bufs& w = plans[i]->w;
+    shapes[k] = nlv::ToepShape{static_cast<double2*>(w.U2), w.P, w.tw, turns[i], s.J, s.B * s.J * s.G};
+  }
+  NLV_HIP(first, nlv::launch_toep_ragged(st, shapes));
+  for (int i = 0; i < count; ++i) {
+    nlinv_plan plan = plans[i];
+    const Shape& s = plan->s;
+    Bufs& w = plan->w;
+    const float2* xh = reinterpret_cast<const float2*>(d_xhat[i]);
+    NLV_HIP(plan, plan->t->cols_back(s, w, st, 0, w.U2, w.CO, xh, nullptr));
+    NLV_HIP(plan, plan->t->coilh_rows(s, w, st, 0, w.Pv[0], xh, nullptr, alpha[i], w.Q, nullptr));
+    NLV_HIP(plan, nlv::launch_finalize(s, w, st, w.Pv[0], alpha[i], reinterpret_cast<float2*>(d_q[i])));
+  }
+  return NLINV_OK;
+}
+
 int nlinv_apply_normal2(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xa, const nlinv_c64* d_xb,
                         double alpha, const double* d_p, double* d_q) {
   NLV_CHECK(check_plan(plan));

@@ -231,6 +231,16 @@ hipError_t launch_nudft_fwd(const Shape& s, hipStream_t st, const float* traj, c
 // PSF kernel of `turn` from the first S samples of traj (S <= s.S)
 hipError_t launch_psf(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn);
 hipError_t launch_kb_table(const Shape& s, const Bufs& w, hipStream_t st, const float* traj, int S, int turn);
+// One shape of a ragged Toeplitz row pass: a plan's half-transformed grid,
+// PSF kernels, twiddles and turns, and its J and line count (B J G).
+struct ToepShape {
+  double2* U2;
+  const float* P;
+  const double2* tw;
+  TurnArgs turns;
+  int J, nlines;
+};
+hipError_t launch_toep_ragged(hipStream_t st, const ToepShape (&shapes)[3]);
 // channel compression y [B][J][S] = cc [J][Jp] x yp [B][Jp][S]; covariance of one frame [Jp][S]
 constexpr int MAX_JP = 128;
 hipError_t launch_compress(const Shape& s, hipStream_t st, const float2* cc, int Jp, const float2* yp, float2* y);

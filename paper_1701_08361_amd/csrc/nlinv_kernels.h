@@ -401,26 +401,23 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
 // operator part of Re<p, q> in the four-pass CG iteration.  KEY names the
 // grid side and the factorisation of its team transform (nlinv_fft.h), so
 // that the factorisation of this pass can be chosen per plan.
-template <int KEY, class S2, bool PQ = false>
-__global__ void __launch_bounds__(row_threads<KEY>())
-k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
-            const double2* __restrict__ tw, int J, int nlines, double* __restrict__ part, int pstride, int nbi) {
+//
+// toep_lines transforms the RT = row_lines<KEY>() lines base .. base+RT-1 of
+// U2 (those below base + nvalid; the other teams only take part in the
+// barriers); every thread of the block calls it.  With PQ, the group's
+// partial goes to *part.  The kernels below map blocks to line groups.
+template <int KEY, class S2, bool PQ>
+__device__ __forceinline__ void toep_lines(C* __restrict__ lds, double* __restrict__ sh, S2* __restrict__ U2,
+                                           const float* __restrict__ P, const TurnArgs& turns,
+                                           const double2* __restrict__ tw, int J, int base, int nvalid,
+                                           double* __restrict__ part) {
   using T = Team<KEY>;
   constexpr int G = grid_of(KEY), R = G / 2, RT = row_lines<KEY>();
-  __shared__ C lds[RT * T::LDSN];
-  __shared__ double sh[64];
   const int rl0 = (int)threadIdx.x / T::SIZE;
-  int row0 = blockIdx.x * RT + rl0;
-  bool inside = row0 < nlines;
-  if constexpr (PQ) {
-    const int ib = blockIdx.x / nbi, lb = blockIdx.x - ib * nbi;
-    row0 = ib * J * G + lb * RT + rl0;
-    inside = lb * RT + rl0 < J * G;
-  }
   // lanes past the last team, or of a team past the last line, only take part in barriers
-  const bool act = rl0 < RT && inside;
+  const bool act = rl0 < RT && rl0 < nvalid;
   const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
-  const int row = act ? row0 : 0;
+  const int row = act ? base + rl0 : 0;
   const int ky = row % G, b = row / G / J;
   S2* line = U2 + (size_t)row * R;
   const float* prow = P + ((size_t)turns.t[b] * G + ky) * G;
@@ -449,12 +446,70 @@ k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
   if constexpr (PQ) {
     static_assert(row_threads<KEY>() == 64, "one wavefront per block");
     const double s = block_sum_waves<64>(acc, sh);
-    if (threadIdx.x == 0) part[(size_t)(blockIdx.x / nbi) * pstride + blockIdx.x % nbi] = s;
+    if (threadIdx.x == 0) *part = s;
   }
   fsB<KEY, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
     const int ix = img_idx<G>(n);
     if (ix >= 0) nt_store(line + ix, store_as<S2>(val));
   });
+}
+
+template <int KEY, class S2, bool PQ = false>
+__global__ void __launch_bounds__(row_threads<KEY>())
+k_toep_rows(S2* __restrict__ U2, const float* __restrict__ P, TurnArgs turns,
+            const double2* __restrict__ tw, int J, int nlines, double* __restrict__ part, int pstride, int nbi) {
+  using T = Team<KEY>;
+  constexpr int G = grid_of(KEY), RT = row_lines<KEY>();
+  __shared__ C lds[RT * T::LDSN];
+  __shared__ double sh[64];
+  if constexpr (PQ) {
+    // blocks per item: nbi groups of RT lines over the item's J G lines, the last one partial
+    const int ib = blockIdx.x / nbi, lb = blockIdx.x - ib * nbi;
+    toep_lines<KEY, S2, true>(lds, sh, U2, P, turns, tw, J, ib * J * G + lb * RT, J * G - lb * RT,
+                              part + (size_t)ib * pstride + lb);
+  } else {
+    toep_lines<KEY, S2, false>(lds, sh, U2, P, turns, tw, J, blockIdx.x * RT, nlines - blockIdx.x * RT, nullptr);
+  }
+}
+
+// One Toeplitz row pass over the plans of several grid sides in a single
+// persistent launch: the line groups of every shape (shape k on its own grid
+// and team, key Kk) form one list of tiles, shape 0's first, and block b of
+// the launch's resident blocks takes tiles b, b + gridDim.x, ... until the
+// list is done.  A shape with no lines is absent.  (A dynamic queue, blocks
+// taking tiles from an atomic counter, was measured slower: the atomics on
+// the one counter serialise, 0.61 against 0.39 ms for the mixed shapes.)
+template <int K0, int K1, int K2>
+constexpr int ragged_lds() {
+  constexpr int a = row_lines<K0>() * Team<K0>::LDSN, b = row_lines<K1>() * Team<K1>::LDSN;
+  constexpr int c = row_lines<K2>() * Team<K2>::LDSN;
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+template <int K0, int K1, int K2>
+__global__ void __launch_bounds__(64)
+k_toep_rows_ragged(ToepShape s0, ToepShape s1, ToepShape s2) {
+  static_assert(row_threads<K0>() == 64 && row_threads<K1>() == 64 && row_threads<K2>() == 64,
+                "one wavefront per tile");
+  __shared__ C lds[ragged_lds<K0, K1, K2>()];
+  __shared__ double sh[64];
+  constexpr int R0 = row_lines<K0>(), R1 = row_lines<K1>(), R2 = row_lines<K2>();
+  const int n0 = (s0.nlines + R0 - 1) / R0, n1 = (s1.nlines + R1 - 1) / R1, n2 = (s2.nlines + R2 - 1) / R2;
+  const int total = n0 + n1 + n2;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {      // block-uniform
+    if (t < n0) {
+      toep_lines<K0, double2, false>(lds, sh, s0.U2, s0.P, s0.turns, s0.tw, s0.J, t * R0, s0.nlines - t * R0,
+                                     nullptr);
+    } else if (t < n0 + n1) {
+      const int u = t - n0;
+      toep_lines<K1, double2, false>(lds, sh, s1.U2, s1.P, s1.turns, s1.tw, s1.J, u * R1, s1.nlines - u * R1,
+                                     nullptr);
+    } else {
+      const int u = t - n0 - n1;
+      toep_lines<K2, double2, false>(lds, sh, s2.U2, s2.P, s2.turns, s2.tw, s2.J, u * R2, s2.nlines - u * R2,
+                                     nullptr);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -935,4 +935,19 @@ hipError_t launch_kb_table(const Shape& s, const Bufs& w, hipStream_t st, const 
   return hipGetLastError();
 }
 
+// The ragged Toeplitz row pass over plans of the grid sides 256, 320 and 384
+// (slot k holds the plan of grid 256, 320 or 384; nlines = 0 for an absent
+// one): one persistent launch over the shapes' tiles.
+hipError_t launch_toep_ragged(hipStream_t st, const ToepShape (&shapes)[3]) {
+  const int tiles = (shapes[0].nlines + row_lines<256>() - 1) / row_lines<256>() +
+                    (shapes[1].nlines + row_lines<320>() - 1) / row_lines<320>() +
+                    (shapes[2].nlines + row_lines<384>() - 1) / row_lines<384>();
+  if (tiles == 0) return hipSuccess;
+  // enough resident blocks to fill the GPU (about 8 per CU at this block's LDS size)
+  constexpr int RESIDENT = 2048;
+  const int blocks = tiles < RESIDENT ? tiles : RESIDENT;
+  k_toep_rows_ragged<256, 320, 384><<<blocks, 64, 0, st>>>(shapes[0], shapes[1], shapes[2]);
+  return hipGetLastError();
+}
+
 }  // namespace nlv

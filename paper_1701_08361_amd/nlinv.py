@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
         "nlinv_apply_EH": [_P, _P, _P, _P],
         "nlinv_nudft": [_P, _P, _P, _P],
         "nlinv_newton_step": [_P, _P, _P, _P, ctypes.c_double, _I, _P],
+        "nlinv_apply_normal_multi": [_I, _P, _P, _P, _P, _P, _P],
         "nlinv_set_coil_weights": [_P, _P],
         "nlinv_compress": [_P, _P, _I, _P, _P],
         "nlinv_compression_matrix": [_P, _P, _I, _P],
@@ -510,3 +511,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def apply_normal_multi(plans, turns, xhats, alphas, ps, qs=None):
+    """The CG operator of several plans of different grid sides (256, 320,
+    384) with one ragged Toeplitz launch (nlinv_apply_normal_multi); equals
+    Plan.apply_normal per plan.  Runs on the first plan's stream."""
+    import torch
+    n = len(plans)
+    if not (len(turns) == len(xhats) == len(alphas) == len(ps) == n):
+        raise ValueError("one turn list, point, alpha and direction per plan")
+    qs = [pl.empty(pl.B, pl.X) for pl in plans] if qs is None else qs
+    for pl, x, p, q in zip(plans, xhats, ps, qs):
+        for t, name in ((x, "xhat"), (p, "p"), (q, "q")):
+            pl._t(t, torch.complex64, (pl.B, pl.X), name)
+    plans[0]._stream_sync()
+    P = ctypes.c_void_p
+    handles = (P * n)(*[pl.handle for pl in plans])
+    tl = [plans[i]._turns(turns[i]) for i in range(n)]
+    tp = (P * n)(*[ctypes.cast(t, P) for t in tl])
+    xp = (P * n)(*[x.data_ptr() for x in xhats])
+    pp = (P * n)(*[p.data_ptr() for p in ps])
+    qp = (P * n)(*[q.data_ptr() for q in qs])
+    ap = (ctypes.c_double * n)(*[float(a) for a in alphas])
+    rc = load().nlinv_apply_normal_multi(n, handles, tp, xp, ap, pp, qp)
+    if rc != OK:
+        msgs = [load().nlinv_last_error(h) for h in [pl.handle for pl in plans] + [None]]
+        msg = next((m.decode() for m in msgs if m), "")
+        raise NlinvError(rc, msg)
+    return qs
