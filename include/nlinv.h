@@ -176,6 +176,10 @@ int nlinv_budget_used(int32_t device, size_t* used_bytes);
  * share one array, so would two of them, which is why only one may live. */
 #define NLINV_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
 int nlinv_plan_create_static(const nlinv_params* p, void* stream, nlinv_plan* out);
+/* Make `stream` (a hipStream_t; NULL = the null stream) the plan's stream for
+ * later calls.  Work already enqueued on the previous stream is not waited
+ * for: the caller orders the two streams (an event) before the next call,
+ * since every call reuses the plan's workspace. */
 int nlinv_set_stream(nlinv_plan plan, void* stream);
 
 /* PSF kernel of one turn (Sec. 2.2 footnote; Fig. flow: convolution with the
