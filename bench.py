@@ -219,12 +219,12 @@ def run_mode(torch, nl, data, B, steps, warmup, timer_kernels, kt_frames, graphs
     return per, total_ms, kt
 
 
-def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None):
+def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None, cg_passes=0):
     """One series under the relaxed temporal coupling: frames 0..l in strict
     order, then groups of o frames (nlinv_reconstruct_frames).  Times the
     groups that start at or after frame `warmup`, about `steps` frames.
     Returns (frames timed, total ms, per-group ms, frames processed)."""
-    plan = nl.Plan(N, J, K, U=U, batch=o, newton=M, cg=C, col_tile=COL_TILE)
+    plan = nl.Plan(N, J, K, U=U, batch=o, newton=M, cg=C, col_tile=COL_TILE, cg_passes=cg_passes)
     plan.set_graphs(graphs)
     traj = torch.from_numpy(data[0][0]).cuda()      # [F, K, S_r, 2]
     y = torch.from_numpy(data[0][1]).cuda()         # [F, J, S]
@@ -280,7 +280,7 @@ def run_relaxed(torch, nl, data, steps, warmup, l, o, graphs, img_store=None):
     return ngroups * o, total, [a.elapsed_time(b) for a, b in ev], n
 
 
-def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs):
+def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs, cg_passes=0):
     """S slices streamed at 1000 / period_ms frames/s each; the S frames of
     period k arrive together at k * period_ms (after 2U untimed warm-up
     periods that capture the graphs).
@@ -291,7 +291,7 @@ def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs):
     Latency = completion (HIP event) - arrival.  Returns (latencies ms,
     frames, wall ms)."""
     B = 1 if policy == "plain" else S
-    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C)
+    plan = nl.Plan(N, J, K, U=U, batch=B, newton=M, cg=C, cg_passes=cg_passes)
     plan.set_graphs(graphs)
     traj = torch.from_numpy(np.stack([d[0] for d in data[:S]], axis=1)).cuda()  # [F,S,K,S_r,2]
     y = torch.from_numpy(np.stack([d[1] for d in data[:S]], axis=1)).cuda()     # [F,S,J,S]
@@ -824,6 +824,10 @@ def main():
                     help="columns per block of the CG column passes (0 = the library's choice)")
     ap.add_argument("--cg-passes-plain", type=int, default=4, choices=[0, 4, 6],
                     help="CG iteration form of the batch-1 plans (4: folded, measured faster at batch 1)")
+    ap.add_argument("--cg-passes-serve", default="4,6",
+                    help="CG iteration forms of the serving run's plain (batch 1) and batched policies")
+    ap.add_argument("--cg-passes-relaxed", type=int, default=4, choices=[0, 4, 6],
+                    help="CG iteration form of the relaxed-coupling plan (batch o, then one frame at a time)")
     ap.add_argument("--cg-passes-batched", type=int, default=6, choices=[0, 4, 6],
                     help="CG iteration form of the batched plans (6: fewer bytes, measured faster at batch 16)")
     ap.add_argument("--fft-split-plain", type=int, default=0, choices=[0, 1],
@@ -916,7 +920,7 @@ def main():
         l, o = args.relaxed_l, args.relaxed_o
         img_rel = torch.zeros_like(img_strict)
         nfr, total, per_g, n_end = run_relaxed(torch, nl, plain_data, args.steps, args.warmup, l, o,
-                                               args.graphs, img_store=img_rel)
+                                               args.graphs, img_store=img_rel, cg_passes=args.cg_passes_relaxed)
         nmax = min(n_end, img_strict.shape[0])
         d = (img_rel[l + 1:nmax] - img_strict[l + 1:nmax]).flatten(1).norm(dim=1) / \
             img_strict[l + 1:nmax].flatten(1).norm(dim=1)
@@ -949,10 +953,12 @@ def main():
         out["hbm_check"] = {"batch": hb, "fps": hb * 2 / (total_hb / 1e3)}
     if batch_data is not None and args.serve_slices > 0:
         S = min(args.serve_slices, len(batch_data))
-        serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods}
-        for policy in ("plain", "batched"):
+        forms = [int(v) for v in args.cg_passes_serve.split(",")]
+        serving = {"slices": S, "fps_per_slice": args.serve_fps, "periods": args.serve_periods,
+                   "cg_passes": {"plain": forms[0], "batched": forms[-1]}}
+        for policy, cp in (("plain", forms[0]), ("batched", forms[-1])):
             lat, nfr, wall = run_serving(torch, nl, batch_data, S, args.serve_periods, 1e3 / args.serve_fps, policy,
-                                         args.graphs)
+                                         args.graphs, cg_passes=cp)
             serving[policy] = {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
                                "frames": nfr, "fps": nfr / (wall / 1e3)}
         out["serving"] = serving
@@ -1005,7 +1011,7 @@ def main():
     out["config"] = {"workload": "real-time series 160px (320 grid), 10 virtual coils, 15 spokes x 320, "
                                  "5 turns, 7 Newton x 20 CG, temporal regularisation",
                      "plain_batch": 1, "batched_batch": args.batch, "cg_passes_plain": args.cg_passes_plain,
-                     "cg_passes_batched": args.cg_passes_batched,
+                     "cg_passes_batched": args.cg_passes_batched, "cg_passes_relaxed": args.cg_passes_relaxed,
                      "fft_split_plain": args.fft_split_plain, "fft_split_batched": args.fft_split_batched,
                      "hip_graphs": args.graphs,
                      "data_gen_s": round(t_gen, 1)}

@@ -79,9 +79,11 @@ class Server:
         return nlinv.workspace_size(p) + 256 + bufs
 
     def admit(self, name: str, N: int, J: int, J_phys: int, K: int, U: int, trajs, calib,
-              newton: int = 7, cg: int = 20):
+              newton: int = 7, cg: int = 20, cg_passes: int = 4):
         """Add a slice.  trajs: device [U][K][S_r][2] trajectories of its turns;
         calib: device [J_phys][S] calibration frame for the channel compression.
+        cg_passes: CG iteration form of the slice's plan (one frame at a time:
+        the four-pass form, measured faster at batch 1).
         Raises BudgetError (and allocates nothing) when the budget would be
         exceeded."""
         torch = self.torch
@@ -96,7 +98,7 @@ class Server:
             copy_stream = torch.cuda.Stream(device=self.device)
             solve_stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(solve_stream):
-            plan = nlinv.Plan(N, J, K, U=U, newton=newton, cg=cg, device=self.device)
+            plan = nlinv.Plan(N, J, K, U=U, newton=newton, cg=cg, device=self.device, cg_passes=cg_passes)
             plan.set_graphs(self.graphs)
             for t in range(U):
                 plan.psf(trajs[t].contiguous(), t)

@@ -41,7 +41,7 @@ def test_server_matches_direct_calls(torch):
                 outs[(n, f)] = outs[(n, f)][1].clone()
         # the same steps through the plan directly
         for (n, j, jp, k), ser in zip(shapes, sers):
-            plan = nlinv.Plan(n, j, k, U=U, newton=M, cg=C)
+            plan = nlinv.Plan(n, j, k, U=U, newton=M, cg=C, cg_passes=4)    # the server's form
             tr = torch.from_numpy(ser.traj).cuda()
             for t in range(U):
                 plan.psf(tr[t].contiguous(), t)
