@@ -327,7 +327,7 @@ def test_unrolled_160px_five_newton_against_oracle_differences(torch):
     derivatives in alpha_0, a and l, and the data gradient's projections on
     eight seeded directions against the oracle's FP64 reconstruction and its
     central differences (tests/golden/unrolled160.json, written by
-    make_unrolled160.py).  The data gradient is judged by
+    make_unrolled160.py).  The data gradient is measured by
     sqrt(sum_k (g.u_k - d_k)^2 / sum_k d_k^2): for random directions both
     sums estimate ||g - grad||^2 and ||grad||^2 up to the same factor, so the
     ratio estimates the gradient's relative error; a single projection can
