@@ -229,6 +229,15 @@ def test_newton_step_equals_the_solvers_steps(torch):
     e = rel(xw.cpu().numpy(), x20.cpu().numpy())
     print(f"coil-weight table (20, 2) vs plan of (20, 2): rel {e:.2e}")
     assert e < 1e-5 and torch.equal(back, own)
+    # with HIP graphs: a captured reconstruction is not replayed with a stale table
+    plan.set_graphs(True)
+    g_own, _, _ = plan.reconstruct(z, [0])
+    plan.set_coil_weights(m.winv)
+    g_w, _, _ = plan.reconstruct(z, [0])
+    plan.set_coil_weights(None)
+    g_back, _, _ = plan.reconstruct(z, [0])
+    torch.cuda.synchronize()
+    assert torch.equal(g_own, own) and torch.equal(g_w, xw) and torch.equal(g_back, own)
     assert rel(own.cpu().numpy(), x20.cpu().numpy()) > 1e-3     # the weight matters
     p20.close()
     plan.close()
