@@ -85,9 +85,10 @@ class _LibraryStep(torch.autograd.Function):
     """One checkpointed Newton step of the Toeplitz form on a library plan.
     Forward: the solver's own Newton step (nlinv_newton_step: its kernels,
     FP64 CG; the iterate rounded to the plan's precision, complex64, as the
-    solver stores it; a reweighted model runs under its coil-weight table).  Backward: the step
-    recomputed with the differentiable operators (newton_step_toeplitz) and
-    differentiated; only the step's inputs are kept in between."""
+    solver stores it; a reweighted model runs under its coil-weight table).
+    Backward: the step recomputed with the differentiable operators
+    (newton_step_toeplitz) and differentiated; only the step's inputs are
+    kept in between."""
 
     @staticmethod
     def forward(ctx, x, xprev, z, alpha, d, plan, turns, cg_iters, R, winv, alpha_value):
