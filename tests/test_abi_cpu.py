@@ -96,6 +96,21 @@ def test_null_plan_rejected(lib):
     assert lib.nlinv_psf_samples(None, None, 1, 0) == nl.E_ARG
     assert lib.nlinv_get_batch(None) == 0
     assert b"NULL" in lib.nlinv_last_error(None)
+    # the entry points of the differentiable form and of the multi-plan operator
+    assert lib.nlinv_newton_step(None, None, None, None, 0.5, 4, None) == nl.E_ARG
+    assert lib.nlinv_set_coil_weights(None, None) == nl.E_ARG
+    assert lib.nlinv_apply_normal2(None, None, None, None, 0.0, None, None) == nl.E_ARG
+    assert lib.nlinv_apply_E(None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_apply_EH(None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_nudft(None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_apply_normal_multi(0, None, None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_apply_normal_multi(4, None, None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_apply_normal_multi(1, None, None, None, None, None, None) == nl.E_ARG
+    assert b"NULL" in lib.nlinv_last_error(None)
+    one = (ctypes.c_void_p * 1)(None)
+    arr = (ctypes.c_void_p * 1)(None)
+    alpha = (ctypes.c_double * 1)(0.0)
+    assert lib.nlinv_apply_normal_multi(1, one, arr, arr, alpha, arr, arr) == nl.E_ARG
 
 
 def test_static_plan_rejects_oversized_parameters(lib):
