@@ -79,12 +79,13 @@ def test_frames_count1_equals_reconstruct(torch):
     assert plan.B == 3
 
 
-@pytest.mark.parametrize("M,l,o", [(3, 2, 3), (1, 0, 2), (2, 1, 4)])
-def test_relaxed_series_matches_oracle(torch, M, l, o):
+@pytest.mark.parametrize("M,l,o,passes", [(3, 2, 3, 6), (1, 0, 2, 6), (2, 1, 4, 6), (3, 2, 3, 4)])
+def test_relaxed_series_matches_oracle(torch, M, l, o, passes):
     """A 9-frame series under h(n, m) with groups of o frames: every frame's
-    image and coil images match the oracle's relaxed schedule."""
+    image and coil images match the oracle's relaxed schedule (both CG
+    iteration forms)."""
     N, J, K, U, C, F = 32, 5, 7, 3, 8, 9
-    print_case("relaxed series", N=N, J=J, K=K, U=U, M=M, C=C, F=F, l=l, o=o)
+    print_case("relaxed series", N=N, J=J, K=K, U=U, M=M, C=C, F=F, l=l, o=o, passes=passes)
     ser = synth.real_time_series(seed=23, N=N, J=J, J_phys=8, K=K, U=U, frames=F)
     g = O.Geometry.make(N, J)
     src = O.relaxed_sources(F, l, o)
@@ -92,7 +93,7 @@ def test_relaxed_series_matches_oracle(torch, M, l, o):
     Ps = [O.psf_kernel(ser.traj[f], g.R, g.G) for f in range(F)]
     ref = O.reconstruct_series(g, zs, Ps, src, newton=M, cg_iters=C)
 
-    plan = nl().Plan(N, J, K, U=U, batch=o, newton=M, cg=C)
+    plan = nl().Plan(N, J, K, U=U, batch=o, newton=M, cg=C, cg_passes=passes)
     z = _grid_all(torch, plan, ser, range(F))
     X = plan.X
     xs = torch.empty(F, X, dtype=torch.complex64, device="cuda")
