@@ -335,12 +335,16 @@ constexpr int cls_n() { return classify(Team<G>::GRID, SET, Team<G>::G1 * N2, Te
 template <int G, int SET, int K1>
 constexpr int cls_k() { return classify(Team<G>::GRID, SET, Team<G>::G2 * K1, Team<G>::G2); }
 
-// runtime twiddle exp(DIR i 2 pi m / G) from the host-built FP64 table tw[m] = (cos, sin)
+// runtime twiddle exp(DIR i 2 pi m / G) from the value v = tw[m] = (cos, sin)
+// of the host-built FP64 table
+template <int DIR, class C>
+__device__ __forceinline__ C twv(double2 v) {
+  using R = typename CT<C>::R;
+  return CT<C>::mk((R)v.x, (R)(DIR > 0 ? v.y : -v.y));
+}
 template <int DIR, class C>
 __device__ __forceinline__ C twr(const double2* __restrict__ tw, int m) {
-  using R = typename CT<C>::R;
-  const double2 v = tw[m];
-  return CT<C>::mk((R)v.x, (R)(DIR > 0 ? v.y : -v.y));
+  return twv<DIR, C>(tw[m]);
 }
 
 // Gather of the fsA inputs of thread tl < G1: a[n2] = x[tl + G1 n2] from
@@ -363,16 +367,18 @@ __device__ __forceinline__ void fsA_load(int tl, C (&a)[Team<G>::G2], Load&& loa
 
 // fsA on gathered inputs a (fsA_load); outputs X[G2 k1 + tl] in out[k1] for
 // tl < G2, outputs outside SET_OUT left zero.  Contains one workgroup barrier;
-// every thread of the block must call it.  a is overwritten.
+// every thread of the block must call it.  a is overwritten.  tv is the
+// thread's twiddle table value tw[tl] (twiddle_of): a kernel that loads it
+// together with its data keeps the table load off the transform's critical path.
 template <int G, int DIR, int SET_OUT, class C>
-__device__ __forceinline__ void fsA_regs(int tl, C* lds, const double2* __restrict__ tw,
-                                         C (&a)[Team<G>::G2], C (&out)[Team<G>::G1]) {
+__device__ __forceinline__ void fsA_regs(int tl, C* lds, double2 tv, C (&a)[Team<G>::G2],
+                                         C (&out)[Team<G>::G1]) {
   using T = Team<G>;
   if (tl < T::G1) {
     DFT<T::G2, DIR, C>::run(a);
     // twiddles w^(tl k2) by recurrence from one table value (FP64: the
     // rounding of the k2-fold product stays near 1e-15, far below float32)
-    const C w1 = twr<DIR, C>(tw, tl);
+    const C w1 = twv<DIR, C>(tv);
     C wk = w1;
     sfor<0, T::G2>([&](auto i) {
       constexpr int k2 = decltype(i)::value;
@@ -398,6 +404,19 @@ __device__ __forceinline__ void fsA_regs(int tl, C* lds, const double2* __restri
   }
 }
 
+// the twiddle table value of team lane tl (also valid for the idle lanes,
+// tl = SIZE < G)
+template <int G>
+__device__ __forceinline__ double2 twiddle_of(const double2* __restrict__ tw, int tl) {
+  return tw[tl];
+}
+
+template <int G, int DIR, int SET_OUT, class C>
+__device__ __forceinline__ void fsA_regs(int tl, C* lds, const double2* __restrict__ tw,
+                                         C (&a)[Team<G>::G2], C (&out)[Team<G>::G1]) {
+  fsA_regs<G, DIR, SET_OUT>(tl, lds, twiddle_of<G>(tw, tl), a, out);
+}
+
 // fsA: inputs x[n1 + G1 n2] from load(n) (thread tl = n1 < G1); outputs
 // X[G2 k1 + tl] in out[k1] for tl < G2.  Inputs outside SET_IN are zero and
 // outputs outside SET_OUT are left zero.  Contains one workgroup barrier;
@@ -415,8 +434,7 @@ __device__ __forceinline__ void fsA(int tl, C* lds, const double2* __restrict__ 
 // thread tl = n1 < G1.  Starts with a barrier so that the LDS line may be
 // reused right after fsA; contains two barriers.
 template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Store>
-__device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ tw,
-                                    C (&in)[Team<G>::G1], Store&& store) {
+__device__ __forceinline__ void fsB(int tl, C* lds, double2 tv, C (&in)[Team<G>::G1], Store&& store) {
   using T = Team<G>;
   __syncthreads();
   if (tl < T::G2) {
@@ -425,7 +443,7 @@ __device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ 
       if constexpr (cls_k<G, SET_IN, k1>() == NEVER) in[k1] = czero<C>();
     });
     DFT<T::G1, DIR, C>::run(in);
-    const C w1 = twr<DIR, C>(tw, tl);   // w^(n1 tl) by recurrence, as in fsA
+    const C w1 = twv<DIR, C>(tv);   // w^(n1 tl) by recurrence, as in fsA
     C wk = w1;
     sfor<0, T::G1>([&](auto i) {
       constexpr int n1 = decltype(i)::value;
@@ -450,6 +468,12 @@ __device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ 
       if constexpr (cls_n<G, SET_OUT, n2>() != NEVER) store(tl + T::G1 * n2, a[n2]);
     });
   }
+}
+
+template <int G, int DIR, int SET_IN, int SET_OUT, class C, class Store>
+__device__ __forceinline__ void fsB(int tl, C* lds, const double2* __restrict__ tw, C (&in)[Team<G>::G1],
+                                    Store&& store) {
+  fsB<G, DIR, SET_IN, SET_OUT>(tl, lds, twiddle_of<G>(tw, tl), in, static_cast<Store&&>(store));
 }
 
 // ---------------------------------------------------------------------------

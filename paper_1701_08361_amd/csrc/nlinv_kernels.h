@@ -163,6 +163,10 @@ __device__ __forceinline__ double2 wave0_sum2_arrays(const double* __restrict__ 
   return make_double2(sh[0], sh[1]);
 }
 
+// partial sums per lane that a pass loads up front for beta (the rest, if
+// any, in a loop after them)
+constexpr int BETA_PRE = 12;
+
 __device__ __forceinline__ double beta_wave0(const Partials& sc, int b, double* sh) {
   const double2 r = wave0_sum2_arrays(sc.cur + (size_t)b * sc.stride, sc.ncur, sc.prev + (size_t)b * sc.stride,
                                       sc.nprev, sh);
@@ -419,10 +423,23 @@ __device__ __forceinline__ void toep_lines(C* __restrict__ lds, double* __restri
   const int tl = act ? (int)threadIdx.x % T::SIZE : T::SIZE, rl = act ? rl0 : 0;
   const int row = act ? base + rl0 : 0;
   const int ky = row % G, b = row / G / J;
+  // the turn of each line's item: a group's lines belong to at most two
+  // consecutive items, whose turns are read from the kernel arguments with
+  // block-uniform indices (scalar loads, not a per-lane memory round trip
+  // ahead of the PSF row loads)
+  const int b0 = __builtin_amdgcn_readfirstlane(base / G / J);
+  const int t0 = turns.t[b0], t1 = turns.t[b0 + 1 < MAXB ? b0 + 1 : b0];
   S2* line = U2 + (size_t)row * R;
-  const float* prow = P + ((size_t)turns.t[b] * G + ky) * G;
+  const float* prow = P + ((size_t)(b == b0 ? t0 : t1) * G + ky) * G;
   C* L = lds + rl * T::LDSN;
-  // PSF kernel values of this thread's spectrum outputs, fetched before the transform
+  // every load of the group is issued before the first wait: the line, the
+  // twiddle value and the PSF kernel values of this thread's spectrum outputs
+  C a[T::G2];
+  fsA_load<KEY, SET_IMG>(tl, a, [&](int n) -> C {
+    const int ix = img_idx<G>(n);
+    return ix < 0 ? czero<C>() : to_d(nt_load(line + ix));
+  });
+  const double2 tv = twiddle_of<KEY>(tw, tl);
   float pk[T::G1];
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
@@ -431,10 +448,7 @@ __device__ __forceinline__ void toep_lines(C* __restrict__ lds, double* __restri
     });
   }
   C v[T::G1];
-  fsA<KEY, -1, SET_IMG, SET_ALL>(tl, L, tw, [&](int n) -> C {
-    const int ix = img_idx<G>(n);
-    return ix < 0 ? czero<C>() : to_d(nt_load(line + ix));
-  }, v);
+  fsA_regs<KEY, -1, SET_ALL>(tl, L, tv, a, v);
   double acc = 0.0;
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
@@ -448,7 +462,7 @@ __device__ __forceinline__ void toep_lines(C* __restrict__ lds, double* __restri
     const double s = block_sum_waves<64>(acc, sh);
     if (threadIdx.x == 0) *part = s;
   }
-  fsB<KEY, +1, SET_ALL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
+  fsB<KEY, +1, SET_ALL, SET_IMG>(tl, L, tv, v, [&](int n, C val) {
     const int ix = img_idx<G>(n);
     if (ix >= 0) nt_store(line + ix, store_as<S2>(val));
   });
@@ -517,7 +531,11 @@ k_toep_rows_ragged(ToepShape s0, ToepShape s1, ToepShape s2) {
 // to the coil rows.  MODE 0 normal, 1 residual z - t, 2 adjoint of `in` (image, float32),
 // 3 plain W^-H column stage of coil images `in` (no channel products, no rho).
 // ---------------------------------------------------------------------------
-template <int G, int TWC, int MODE, class S2>
+// EARLY (the four-pass CG form, whose batch-1 chain is latency-bound): the
+// coil image and rho values are loaded together with the column, so that the
+// pass has one memory round trip before its first transform and none after it
+// (at the cost of registers: 2 waves per SIMD instead of 3)
+template <int G, int TWC, int MODE, class S2, bool EARLY = false>
 __global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
             const float2* __restrict__ z, const double2* __restrict__ tw, float2* __restrict__ PR,
@@ -546,10 +564,30 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   C* L = lds + col * T::LDSC;
   const size_t img = (size_t)bj * R * R;
 
+  const double2 tv = twiddle_of<G>(tw, tl);
+  const float2* rho = xh + (size_t)b * X;
   C v[T::G1];
+  float2 cov[T::G1], rov[T::G1];
   if constexpr (MODE < 2) {
     const S2* c0 = static_cast<const S2*>(inp) + (size_t)bj * G * R + x;
-    fsA<G, +1, SET_ALL, SET_IMG>(tl, L, tw, [&](int n) -> C { return to_d(nt_load(c0 + (size_t)n * R)); }, v);
+    C a[T::G2];
+    fsA_load<G, SET_ALL>(tl, a, [&](int n) -> C { return to_d(nt_load(c0 + (size_t)n * R)); });
+    if constexpr (EARLY) {
+      static_assert(MODE == 0, "the early loads serve the normal operator");
+      // every lane loads (rows outside the image clamped to row 0, never
+      // used): a value defined on every path is converted where it is used,
+      // so no conversion waits on a load while other loads are still to issue
+      sfor<0, T::G1>([&](auto c) {
+        constexpr int k1 = decltype(c)::value;
+        if constexpr (cls_k<G, SET_IMG, k1>() != NEVER) {
+          const int iy = img_idx<G>(T::G2 * k1 + tl);
+          const size_t e = (size_t)(iy >= 0 ? iy : 0) * R + x;
+          cov[k1] = co[img + e];
+          rov[k1] = rho[e];
+        }
+      });
+    }
+    fsA_regs<G, +1, SET_IMG>(tl, L, tv, a, v);
   } else {
     const float2* in = static_cast<const float2*>(inp);
     if (tl < T::G2) {
@@ -561,7 +599,6 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
     }
   }
 
-  const float2* rho = xh + (size_t)b * X;
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
@@ -574,15 +611,15 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
           s = t;   // plain W^-H of a coil image: no channel products
         } else {
           if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
-          PR[img + e] = to_f(cjmul(to_d(co[img + e]), t));
-          s = cjmul(to_d(rho[e]), t);
+          PR[img + e] = to_f(cjmul(to_d(EARLY ? cov[k1] : co[img + e]), t));
+          s = cjmul(to_d(EARLY ? rov[k1] : rho[e]), t);
         }
       }
       v[k1] = s;
     });
   }
   double2* o = U4 + (size_t)bj * GC * R + x;
-  fsB<G, -1, SET_IMG, SET_COIL>(tl, L, tw, v, [&](int n, C val) {
+  fsB<G, -1, SET_IMG, SET_COIL>(tl, L, tv, v, [&](int n, C val) {
     const int i = coil_idx<G>(n);
     if (i >= 0) o[(size_t)i * R] = val;
   });
@@ -743,19 +780,41 @@ template <int G, int TWC, class S2>
 __global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const float2* __restrict__ co,
               const float2* __restrict__ xh, const double2* __restrict__ Rv, const double2* __restrict__ Pold,
-              double2* __restrict__ Pnew, Partials sc, double* __restrict__ ppp, int spp,
-              const double2* __restrict__ tw, S2* __restrict__ U2, int J, long long X, int first) {
+              double2* __restrict__ Pnew, Partials sc, const double2* __restrict__ scal,
+              double* __restrict__ ppp, int spp, const double2* __restrict__ tw, S2* __restrict__ U2, int J,
+              long long X, int first) {
   using T = Team<G>;
   constexpr int R = G / 2, GC = G / 4, NT = R / TWC, NTH = cols_threads<G, TWC>();
+  constexpr int MC = (GC / 2 + T::SIZE - 1) / T::SIZE;   // coil-block entries per lane
   __shared__ C lds[TWC * T::LDSC];
-  __shared__ double sh[2 * (NTH / 64)];
+  __shared__ double sh[1];
   const bool act = (int)threadIdx.x < TWC * T::SIZE;
   const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
   const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J, j = bj - b * J;
   const int x = tile * TWC + col;
   C* L = lds + col * T::LDSC;
+  const size_t xb = (size_t)b * X;
 
-  // x-stage rows of r_i and of p_{i-1} at this column, rho and the coil image
+  // Every load of the block is issued before the first wait, so that the
+  // pass has one memory round trip ahead of its first transform and none
+  // after it (at batch 1 the CG iteration is a chain of such round trips;
+  // the registers this takes leave 2 waves per SIMD instead of 3): the
+  // partial sums behind beta (first wavefront), the CG scalars, the x-stage
+  // rows of r_i and p_{i-1} at this column, the twiddle value, the residual
+  // and old direction of the image and coil blocks, and rho and the coil image.
+  double ps[BETA_PRE];
+  const bool w0 = threadIdx.x < 64;
+  const double* pcur = sc.cur + (size_t)b * sc.stride;
+  if (!first && w0) {
+    sfor<0, BETA_PRE>([&](auto c) {
+      constexpr int k = decltype(c)::value;
+      const int i = (int)threadIdx.x + 64 * k;
+      ps[k] = i < sc.ncur ? pcur[i] : 0.0;
+    });
+  }
+  // rr_{i-1}: the reducing block of the previous iteration's back column pass
+  // summed the same partials in the same order
+  const double rr_prev = first ? 0.0 : scal[b].y;
   const size_t vo = (size_t)bj * GC * R + x;
   C a[T::G2], vp[T::G2];
   if (tl < T::G1) {
@@ -772,9 +831,36 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
       }
     });
   }
-  const float2* rho = xh + (size_t)b * X;
+  const double2 tv = twiddle_of<G>(tw, tl);
+  // coil block of p_i: column x takes half of coil row x / 2 (R = 2 G_c), and
+  // every partial below covers one column, so the sums do not depend on the
+  // tile schedule (every schedule gives the same bits)
+  const size_t e0 = xb + (size_t)R * R + ((size_t)j * GC + (x >> 1)) * GC + (x & 1) * (GC / 2);
+  const float2* rho = xh + xb;
   const float2* cj = co + (size_t)bj * R * R;
-  float2 rv[T::G1], cv[T::G1];
+  double2 rv[T::G1], po[T::G1], crv[MC], cpo[MC];
+  float2 rov[T::G1], cv[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int iy = img_idx<G>(T::G2 * k1 + tl);
+      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) {
+        const size_t e = xb + (size_t)iy * R + x;
+        rv[k1] = Rv[e];
+        if (!first) po[k1] = Pold[e];
+      }
+    });
+  }
+  if (act) {
+    sfor<0, MC>([&](auto c) {
+      constexpr int k = decltype(c)::value;
+      const int m = tl + T::SIZE * k;
+      if (m < GC / 2) {
+        crv[k] = Rv[e0 + m];
+        if (!first) cpo[k] = Pold[e0 + m];
+      }
+    });
+  }
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
@@ -782,13 +868,27 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
         const int iy = img_idx<G>(T::G2 * k1 + tl);
         if (iy >= 0) {
           const size_t e = (size_t)iy * R + x;
-          rv[k1] = rho[e];
+          rov[k1] = rho[e];
           cv[k1] = cj[e];
         }
       }
     });
   }
-  const double beta = first ? 0.0 : beta_wave0(sc, b, sh);
+  // beta = rr_i / rr_{i-1}: the first wavefront sums the partials of rr_i in
+  // index order (the order of every other reduction of these partials),
+  // whatever the block size
+  double beta = 0.0;
+  if (!first) {
+    if (w0) {
+      double su = 0.0;
+      sfor<0, BETA_PRE>([&](auto c) { su += ps[decltype(c)::value]; });
+      for (int i = (int)threadIdx.x + 64 * BETA_PRE; i < sc.ncur; i += 64) su += pcur[i];
+      for (int off = 32; off > 0; off >>= 1) su += __shfl_down(su, off, 64);
+      if (threadIdx.x == 0) sh[0] = su;
+    }
+    __syncthreads();
+    beta = rr_prev != 0.0 ? sh[0] / rr_prev : 0.0;
+  }
   // V_p = V_r + beta V_p: the x-stage of W^-1 p_i, kept for the next iteration
   if (tl < T::G1) {
     sfor<0, T::G2>([&](auto c) {
@@ -802,49 +902,51 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
       }
     });
   }
-  C v[T::G1];
-  fsA_regs<G, +1, SET_IMG>(tl, L, tw, a, v);
-  // image block of p_i at this column (written once, by the channel-0 blocks)
+  // image block of p_i at this column (written once, by the channel-0 blocks),
+  // and its product with the coil image, formed before the transform so that
+  // the residual values need not be held through it
   double acc = 0.0;
-  const size_t xb = (size_t)b * X;
+  C cp[T::G1];
+  if (tl < T::G2) {
+    sfor<0, T::G1>([&](auto c) {
+      constexpr int k1 = decltype(c)::value;
+      const int iy = img_idx<G>(T::G2 * k1 + tl);
+      cp[k1] = czero<C>();
+      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) {
+        double2 dp = rv[k1];
+        if (!first) dp = make_double2(dp.x + beta * po[k1].x, dp.y + beta * po[k1].y);
+        if (j == 0) {
+          Pnew[xb + (size_t)iy * R + x] = dp;
+          acc += dp.x * dp.x + dp.y * dp.y;
+        }
+        cp[k1] = cmul(to_d(cv[k1]), dp);
+      }
+    });
+  }
+  C v[T::G1];
+  fsA_regs<G, +1, SET_IMG>(tl, L, tv, a, v);
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
       constexpr int k1 = decltype(c)::value;
       const int iy = img_idx<G>(T::G2 * k1 + tl);
       C u = czero<C>();
-      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) {
-        const size_t e = xb + (size_t)iy * R + x;
-        double2 dp = Rv[e];
-        if (!first) {
-          const double2 po = Pold[e];
-          dp = make_double2(dp.x + beta * po.x, dp.y + beta * po.y);
-        }
-        if (j == 0) {
-          Pnew[e] = dp;
-          acc += dp.x * dp.x + dp.y * dp.y;
-        }
-        u = cadd(cmul(to_d(cv[k1]), dp), cmul(to_d(rv[k1]), v[k1]));
-      }
+      if (cls_k<G, SET_IMG, k1>() != NEVER && iy >= 0) u = cadd(cp[k1], cmul(to_d(rov[k1]), v[k1]));
       v[k1] = u;
     });
   }
   S2* o = U2 + (size_t)bj * G * R + x;
-  fsB<G, -1, SET_IMG, SET_ALL>(tl, L, tw, v, [&](int n, C val) { nt_store(o + (size_t)n * R, store_as<S2>(val)); });
-  // coil block of p_i: column x takes half of coil row x / 2 (R = 2 G_c), and
-  // every partial below covers one column, so the sums do not depend on the
-  // tile schedule (every schedule gives the same bits)
+  fsB<G, -1, SET_IMG, SET_ALL>(tl, L, tv, v, [&](int n, C val) { nt_store(o + (size_t)n * R, store_as<S2>(val)); });
   if (act) {
-    const int i = x >> 1;
-    const size_t e0 = xb + (size_t)R * R + ((size_t)j * GC + i) * GC + (x & 1) * (GC / 2);
-    for (int m = tl; m < GC / 2; m += T::SIZE) {
-      double2 p = Rv[e0 + m];
-      if (!first) {
-        const double2 po = Pold[e0 + m];
-        p = make_double2(p.x + beta * po.x, p.y + beta * po.y);
+    sfor<0, MC>([&](auto c) {
+      constexpr int k = decltype(c)::value;
+      const int m = tl + T::SIZE * k;
+      if (m < GC / 2) {
+        double2 p = crv[k];
+        if (!first) p = make_double2(p.x + beta * cpo[k].x, p.y + beta * cpo[k].y);
+        Pnew[e0 + m] = p;
+        acc += p.x * p.x + p.y * p.y;
       }
-      Pnew[e0 + m] = p;
-      acc += p.x * p.x + p.y * p.y;
-    }
+    });
   }
   // |p_i|^2 partial of each column: its lanes in lane order
   __shared__ double shc[NTH];
@@ -870,30 +972,53 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
   __shared__ C lds[RT * T::LDSN];
   __shared__ double sh[NTH];
   const int b = blockIdx.x / (nb + nr), chunk = blockIdx.x - b * (nb + nr);
-  const double2 sv = scal[b];                        // (Re<p, q>, rr_i)
-  const double a = sv.x != 0.0 ? sv.y / sv.x : 0.0;
+  // In both block kinds every load is issued before the first wait (one
+  // memory round trip; the CG scalars, which only the arithmetic needs, last).
   if (chunk >= nb) {   // block-uniform: image block, one pixel per lane
     const int e = (chunk - nb) * NTH + (int)threadIdx.x;
+    const bool in = e < R * R;
+    const size_t ve = (size_t)b * X + e;
+    // the first JP channel products are loaded up front (channel indices
+    // clamped to J - 1, so that no load waits on a branch; only k < J is
+    // summed), the rest after them
+    constexpr int JP = 16;
+    float2 pr[JP];
+    double2 p, h, r;
+    float2 xv;
+    if (in) {
+      sfor<0, JP>([&](auto c) {
+        constexpr int k = decltype(c)::value;
+        pr[k] = PR[((size_t)b * J + (k < J ? k : J - 1)) * R * R + e];
+      });
+      p = Pn[ve];
+      h = first ? make_double2(0.0, 0.0) : H[ve];
+      if (last) xv = xh[ve];
+      else r = Rv[ve];
+    }
+    const double2 sv = scal[b];                        // (Re<p, q>, rr_i)
+    const double a = sv.x != 0.0 ? sv.y / sv.x : 0.0;
     double acc = 0.0;
-    if (e < R * R) {
-      const size_t ve = (size_t)b * X + e;
-      const double2 p = Pn[ve];
-      double qx = 0.0, qy = 0.0;
-      for (int j = 0; j < J; ++j) {
-        const float2 pr = PR[((size_t)b * J + j) * R * R + e];
-        qx += pr.x;
-        qy += pr.y;
+    if (in) {
+      double qx = 0.0, qy = 0.0;   // channel sum in channel order
+      sfor<0, JP>([&](auto c) {
+        constexpr int k = decltype(c)::value;
+        if (k < J) {
+          qx += pr[k].x;
+          qy += pr[k].y;
+        }
+      });
+      for (int j = JP; j < J; ++j) {
+        const float2 t = PR[((size_t)b * J + j) * R * R + e];
+        qx += t.x;
+        qy += t.y;
       }
       qx += alpha * p.x;
       qy += alpha * p.y;
-      double2 h = first ? make_double2(0.0, 0.0) : H[ve];
       h = make_double2(h.x + a * p.x, h.y + a * p.y);
       if (last) {
-        const float2 xv = xh[ve];
         xh[ve] = make_float2((float)(xv.x + h.x), (float)(xv.y + h.y));
       } else {
         H[ve] = h;
-        double2 r = Rv[ve];
         r = make_double2(r.x - a * qx, r.y - a * qy);
         Rv[ve] = r;
         acc = r.x * r.x + r.y * r.y;
@@ -913,6 +1038,12 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
   const double2* line = U4 + ((size_t)bj * GC + i) * R;
   const size_t base = (size_t)b * X + (size_t)R * R + ((size_t)j * GC + i) * GC;
   const float* dw = dinv + i * GC;
+  C ln[T::G2];
+  fsA_load<G, SET_IMG>(tl, ln, [&](int n) -> C {
+    const int ix = img_idx<G>(n);
+    return ix < 0 ? czero<C>() : line[ix];
+  });
+  const double2 tv = twiddle_of<G>(tw, tl);
   float wv[T::G1];
   double2 pvv[T::G1], hv[T::G1], rvv[T::G1];
   float2 xv[T::G1];
@@ -931,12 +1062,11 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
       }
     });
   }
+  const double2 sv = scal[b];                        // (Re<p, q>, rr_i)
+  const double a = sv.x != 0.0 ? sv.y / sv.x : 0.0;
   C* L = lds + rl * T::LDSN;
   C v[T::G1];
-  fsA<G, -1, SET_IMG, SET_COIL>(tl, L, tw, [&](int n) -> C {
-    const int ix = img_idx<G>(n);
-    return ix < 0 ? czero<C>() : line[ix];
-  }, v);
+  fsA_regs<G, -1, SET_COIL>(tl, L, tv, ln, v);
   double acc = 0.0;
   if (tl < T::G2) {
     sfor<0, T::G1>([&](auto c) {
@@ -964,7 +1094,7 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
   }
   if (!last) {   // uniform
     double2* o = Vr + ((size_t)bj * GC + i) * R;
-    fsB<G, +1, SET_COIL, SET_IMG>(tl, L, tw, v, [&](int n, C val) {
+    fsB<G, +1, SET_COIL, SET_IMG>(tl, L, tv, v, [&](int n, C val) {
       const int ix = img_idx<G>(n);
       if (ix >= 0) o[ix] = val;
     });
@@ -1294,7 +1424,8 @@ struct GLaunch {
     constexpr int TH = cols_threads<G, TWC>();
     const int blocks = s.B * s.J * (s.R / TWC);
     return launch_timed(w, k_cg_cols_fwd<G, TWC, S2>, dim3(blocks), dim3(TH), 0, st, (const double2*)w.Vr, w.Vp,
-                        (const float2*)w.CO, xh, (const double2*)w.Rv, pold, pnew, sc, w.ppp, s.NPP,
+                        (const float2*)w.CO, xh,
+                        (const double2*)w.Rv, pold, pnew, sc, (const double2*)w.scal, w.ppp, s.NPP,
                         (const double2*)w.tw, static_cast<S2*>(w.U2), s.J, (long long)s.X, first);
   }
   template <class S2>
@@ -1326,7 +1457,7 @@ struct GLaunch {
     const int blocks = s.B * s.J * (s.R / TWC);
     CGRed r = red;
     r.nbase = blocks;   // one reducing block per item after the pass's blocks
-    return launch_timed(w, k_cols_back<G, TWC, 0, S2>, dim3(blocks + s.B), dim3(TH), 0, st, (const void*)w.U2,
+    return launch_timed(w, k_cols_back<G, TWC, 0, S2, true>, dim3(blocks + s.B), dim3(TH), 0, st, (const void*)w.U2,
                         (const float2*)w.CO, xh, (const float2*)nullptr, (const double2*)w.tw, w.PR, w.U1, s.J,
                         (long long)s.X, r);
   }
