@@ -611,7 +611,9 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
           s = t;   // plain W^-H of a coil image: no channel products
         } else {
           if constexpr (MODE == 1) t = csub(to_d(z[img + e]), t);
-          PR[img + e] = to_f(cjmul(to_d(EARLY ? cov[k1] : co[img + e]), t));
+          const float2 pv = to_f(cjmul(to_d(EARLY ? cov[k1] : co[img + e]), t));
+          if constexpr (EARLY) nt_store(PR + img + e, pv);
+          else PR[img + e] = pv;
           s = cjmul(to_d(EARLY ? rov[k1] : rho[e]), t);
         }
       }
@@ -621,7 +623,10 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   double2* o = U4 + (size_t)bj * GC * R + x;
   fsB<G, -1, SET_IMG, SET_COIL>(tl, L, tv, v, [&](int n, C val) {
     const int i = coil_idx<G>(n);
-    if (i >= 0) o[(size_t)i * R] = val;
+    if (i >= 0) {
+      if constexpr (EARLY) nt_store(o + (size_t)i * R, val);
+      else o[(size_t)i * R] = val;
+    }
   });
 }
 
@@ -897,7 +902,7 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
         const int i = coil_idx<G>(tl + T::G1 * n2);
         if (i >= 0) {
           a[n2] = make_double2(a[n2].x + beta * vp[n2].x, a[n2].y + beta * vp[n2].y);
-          Vp[vo + (size_t)i * R] = a[n2];
+          nt_store(Vp + vo + (size_t)i * R, a[n2]);
         }
       }
     });
@@ -916,7 +921,7 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
         double2 dp = rv[k1];
         if (!first) dp = make_double2(dp.x + beta * po[k1].x, dp.y + beta * po[k1].y);
         if (j == 0) {
-          Pnew[xb + (size_t)iy * R + x] = dp;
+          nt_store(Pnew + xb + (size_t)iy * R + x, dp);
           acc += dp.x * dp.x + dp.y * dp.y;
         }
         cp[k1] = cmul(to_d(cv[k1]), dp);
@@ -943,7 +948,7 @@ k_cg_cols_fwd(const double2* __restrict__ Vr, double2* __restrict__ Vp, const fl
       if (m < GC / 2) {
         double2 p = crv[k];
         if (!first) p = make_double2(p.x + beta * cpo[k].x, p.y + beta * cpo[k].y);
-        Pnew[e0 + m] = p;
+        nt_store(Pnew + e0 + m, p);
         acc += p.x * p.x + p.y * p.y;
       }
     });
@@ -1016,11 +1021,11 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
       qy += alpha * p.y;
       h = make_double2(h.x + a * p.x, h.y + a * p.y);
       if (last) {
-        xh[ve] = make_float2((float)(xv.x + h.x), (float)(xv.y + h.y));
+        nt_store(xh + ve, make_float2((float)(xv.x + h.x), (float)(xv.y + h.y)));
       } else {
-        H[ve] = h;
+        nt_store(H + ve, h);
         r = make_double2(r.x - a * qx, r.y - a * qy);
-        Rv[ve] = r;
+        nt_store(Rv + ve, r);
         acc = r.x * r.x + r.y * r.y;
       }
     }
@@ -1080,11 +1085,11 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
         const double2 q = make_double2(w.x + alpha * p.x, w.y + alpha * p.y);
         const double2 h = make_double2(hv[k1].x + a * p.x, hv[k1].y + a * p.y);
         if (last) {
-          xh[e] = make_float2((float)(xv[k1].x + h.x), (float)(xv[k1].y + h.y));
+          nt_store(xh + e, make_float2((float)(xv[k1].x + h.x), (float)(xv[k1].y + h.y)));
         } else {
-          H[e] = h;
+          nt_store(H + e, h);
           const double2 r = make_double2(rvv[k1].x - a * q.x, rvv[k1].y - a * q.y);
-          Rv[e] = r;
+          nt_store(Rv + e, r);
           acc += r.x * r.x + r.y * r.y;
           nv = cscale(r, (double)wv[k1]);   // input of the x-stage of W^-1 r_{i+1}
         }
@@ -1096,7 +1101,7 @@ k_cg_coilh(const double2* __restrict__ U4, const float* __restrict__ dinv, const
     double2* o = Vr + ((size_t)bj * GC + i) * R;
     fsB<G, +1, SET_COIL, SET_IMG>(tl, L, tv, v, [&](int n, C val) {
       const int ix = img_idx<G>(n);
-      if (ix >= 0) o[ix] = val;
+      if (ix >= 0) nt_store(o + ix, val);
     });
     const double s = block_sum_waves<NTH>(acc, sh);
     if (threadIdx.x == 0) rr_next[(size_t)b * stride + chunk] = s;
