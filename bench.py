@@ -186,8 +186,9 @@ def run_mode(torch, nl, data, B, steps, warmup, timer_kernels, kt_frames, graphs
     xprev = None
     bufs = [xa, xb]
     # with HIP graphs, every (turn, buffer parity) argument set is captured
-    # before the clock starts, whatever the warm-up count
-    nwarm = max(warmup, 2 * U) if graphs else warmup
+    # before the clock starts, whatever the warm-up count: frame 0 starts from
+    # the unit point, frames 1 .. 2U see every set of the regularised frames
+    nwarm = max(warmup, 2 * U + 1) if graphs else warmup
     for n in range(nwarm):
         frame(n, xprev, bufs[n & 1])
         xprev = bufs[n & 1]
@@ -353,10 +354,13 @@ def run_serving(torch, nl, data, S, periods, period_ms, policy, graphs, cg_passe
     return lat, S * periods, wall
 
 
-def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
+def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs, one_graph=False):
     """Series of several shapes advanced together, one batched plan per shape:
-    one after another on one stream, or each on its own HIP stream so that
-    their kernels overlap.  groups: [(N, J, K, data)].  Returns per-step ms."""
+    one after another on one stream, each on its own HIP stream so that their
+    kernels overlap, or (one_graph) every shape's reconstruction in one HIP
+    graph launch with one independent branch per plan (nlinv_reconstruct_multi,
+    after each plan's gridding on the same stream).  groups: [(N, J, K, data)].
+    Returns per-step ms."""
     runs = []
     for (n, j, k, data) in groups:
         B = len(data)
@@ -374,16 +378,29 @@ def run_mixed(torch, nl, groups, steps, warmup, concurrent, graphs):
     torch.cuda.synchronize()
 
     def step(i):
+        tns = []
         for r in runs:
             f = i % r["traj"].shape[0]
             tn = [int(r["turn"][f])] * r["B"]
+            tns.append(tn)
             with torch.cuda.stream(r["st"]):
                 r["plan"].grid(r["traj"][f], r["y"][f], turns=tn, z=r["z"])
-                prev = None if i == 0 else r["xs"][(i - 1) & 1]
-                r["plan"].reconstruct(r["z"], tn, xprev=prev, xhat=r["xs"][i & 1], init=1 if i == 0 else 2,
-                                      img=r["img"])
+                if not one_graph:
+                    prev = None if i == 0 else r["xs"][(i - 1) & 1]
+                    r["plan"].reconstruct(r["z"], tn, xprev=prev, xhat=r["xs"][i & 1], init=1 if i == 0 else 2,
+                                          img=r["img"])
+        if one_graph:
+            nl.reconstruct_multi([r["plan"] for r in runs], [r["z"] for r in runs], tns,
+                                 xprevs=[None if i == 0 else r["xs"][(i - 1) & 1] for r in runs],
+                                 xhats=[r["xs"][i & 1] for r in runs], inits=[1 if i == 0 else 2] * len(runs),
+                                 imgs=[r["img"] for r in runs])
         torch.cuda.synchronize()
 
+    # graphs (the plans' own or the one-graph form) are captured per (turn,
+    # buffer parity) argument set: frame 0 starts from the unit point, frames
+    # 1 .. 2U see every set of the regularised frames, all before the clock
+    if graphs or one_graph:
+        warmup = max(warmup, 2 * U + 1)
     for i in range(warmup):
         step(i)
     per = []
@@ -482,6 +499,8 @@ def run_mixed_one_launch(torch, nl, groups, steps, warmup, graphs):
         plan.reconstruct(z, tn, xprev=prev, xhat=xs[i & 1], init=1 if i == 0 else 2, img=img)
         torch.cuda.synchronize()
 
+    if graphs:   # every (turn, buffer parity) argument set captured before the clock
+        warmup = max(warmup, 2 * U + 1)
     for i in range(warmup):
         step(i)
     per = []
@@ -992,10 +1011,12 @@ def main():
         nfr = sum(len(g[3]) for g in mixed_data)
         mixed = {"shapes": [{"N": n, "J": j, "K": k, "series": len(d)} for (n, j, k, d) in mixed_data],
                  "frames_per_step": nfr}
-        for name, conc in (("one_stream", False), ("streams", True)):
-            per = run_mixed(torch, nl, mixed_data, args.mixed_steps, 2 * U, conc, args.graphs)
+        for name, conc, one in (("one_stream", False, False), ("streams", True, False), ("one_graph", False, True)):
+            per = run_mixed(torch, nl, mixed_data, args.mixed_steps, 2 * U, conc, args.graphs, one_graph=one)
             mixed[name] = {"fps": nfr / (sum(per) / len(per) / 1e3), "ms_per_step": {"p50": pct(per, 50),
                                                                                     "p99": pct(per, 99)}}
+        mixed["one_graph"]["form"] = ("each shape's gridding, then every shape's reconstruction as one HIP graph "
+                                      "launch with one branch per plan (nlinv_reconstruct_multi), all on one stream")
         per = run_mixed_one_launch(torch, nl, mixed_data, args.mixed_steps, 2 * U, args.graphs)
         mixed["one_launch"] = {"fps": nfr / (sum(per) / len(per) / 1e3),
                                "ms_per_step": {"p50": pct(per, 50), "p99": pct(per, 99)},

@@ -290,6 +290,30 @@ int nlinv_apply_DFH(nlinv_plan plan, const float* d_traj, const nlinv_c64* d_xha
 int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_xhat,
                        double alpha, const nlinv_c64* d_p, nlinv_c64* d_q);
 
+/* One frame on each of several plans as one launch (Sec. 3.3, real-time
+ * series of different image sides, channel and spoke counts, each on its own
+ * plan and grid, without padding to one shape).  The launch sequences
+ * nlinv_reconstruct would enqueue for the plans are captured once per argument
+ * set into one HIP graph whose branches (one per plan) depend on nothing but
+ * the graph's start, and the graph is launched on plans[0]'s stream; the
+ * branches may run concurrently.  Each plan's result equals its own
+ * nlinv_reconstruct bit for bit.
+ *   count        1..NLINV_MAX_MULTI distinct plans, all on one device
+ *   d_z[i], h_turn[i], d_xprev[i], d_xhat[i], init[i], d_img[i]
+ *                plan i's arguments as nlinv_reconstruct takes them (d_xprev[i]
+ *                and d_img[i] may be NULL; no coil-image output); the arrays
+ *                themselves are host memory and not kept
+ * Everything runs on plans[0]'s stream: work pending on the plans' own
+ * streams must be ordered before the call by the caller.  The instantiated
+ * graphs are kept per argument set (at most 64 sets in the process, then all
+ * are dropped), and those of a plan are dropped when it is destroyed or its
+ * coil weights change.  NLINV_E_STATE while a kernel timer is armed on one of
+ * the plans; NLINV_E_ARG for a plan given twice or plans on different devices. */
+#define NLINV_MAX_MULTI 8
+int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_c64* const* d_z,
+                            const int32_t* const* h_turn, const nlinv_c64* const* d_xprev,
+                            nlinv_c64* const* d_xhat, const int32_t* init, float* const* d_img);
+
 /* The CG operator of several plans of different grid sides in one go (the
  * same result as nlinv_apply_normal per plan, bit for bit): every plan's
  * passes run on plans[0]'s stream, and the Toeplitz row passes of all of

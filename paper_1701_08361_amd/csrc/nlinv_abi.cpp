@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,6 +51,8 @@ struct nlinv_plan_s {
   size_t ws_need = 0;           // its workspace size (counted against the device's budget)
   bool is_static = false;       // workspace = the device's static array (nlinv_plan_create_static)
   float* dinv_own = nullptr;    // the plan's own coil-weight table (nlinv_set_coil_weights restores it)
+  uint64_t id = 0;              // unique over the process (keys of the multi-plan graphs)
+  uint64_t gen = 0;             // bumped when the plan's captured graphs go stale
 };
 
 namespace {
@@ -63,6 +66,17 @@ std::mutex g_dev_mu;
 size_t g_budget[MAX_DEV] = {};       // 0: no cap
 size_t g_used[MAX_DEV] = {};         // summed workspace sizes of the live plans
 nlinv_plan g_static_owner[MAX_DEV] = {};
+
+// Graphs of nlinv_reconstruct_multi, one per argument set of a group of plans
+// (keyed by plan ids and generations, so a destroyed plan's address reused by a
+// new plan never meets an old graph); dropped with any member plan.
+std::atomic<uint64_t> g_next_id{1};
+struct MultiGraph {
+  hipGraphExec_t exec;
+  std::vector<uint64_t> ids;
+};
+std::mutex g_multi_mu;
+std::map<std::vector<uint64_t>, MultiGraph> g_multi;
 
 int fail(nlinv_plan plan, int code, const std::string& msg) {
   if (plan) plan->err = msg; else g_err = msg;
@@ -449,6 +463,7 @@ static int create_plan(const nlinv_params* p, void* stream, void* d_workspace, s
     if (is_static) g_static_owner[dev] = plan;
   }
   plan->device = dev;
+  plan->id = g_next_id++;
   plan->ws_need = L.total;
   plan->is_static = is_static;
   plan->p = *p;
@@ -578,6 +593,18 @@ int nlinv_plan_destroy(nlinv_plan plan) {
   if (!plan) return fail(nullptr, NLINV_E_ARG, "plan is NULL");
   for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
   for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    for (auto it = g_multi.begin(); it != g_multi.end();) {
+      const auto& ids = it->second.ids;
+      if (std::find(ids.begin(), ids.end(), plan->id) != ids.end()) {
+        (void)hipGraphExecDestroy(it->second.exec);
+        it = g_multi.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   release_plan(plan);
   return NLINV_OK;
@@ -828,6 +855,115 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
   return check_finite(plan, xh, (long long)plan->s.B * plan->s.X);
 }
 
+int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_c64* const* d_z,
+                            const int32_t* const* h_turn, const nlinv_c64* const* d_xprev,
+                            nlinv_c64* const* d_xhat, const int32_t* init, float* const* d_img) {
+  if (count < 1 || count > NLINV_MAX_MULTI) return fail(nullptr, NLINV_E_ARG, "count must be in [1, 8]");
+  if (!plans || !d_z || !h_turn || !d_xprev || !d_xhat || !init || !d_img)
+    return fail(nullptr, NLINV_E_ARG, "NULL array");
+  std::vector<nlv::TurnArgs> turns(count);
+  std::vector<uint64_t> key = {(uint64_t)count};
+  std::vector<uint64_t> ids;
+  for (int i = 0; i < count; ++i) {
+    nlinv_plan plan = plans[i];
+    NLV_CHECK(check_plan(plan));
+    for (int k = 0; k < i; ++k)
+      if (plans[k] == plan) return fail(plan, NLINV_E_ARG, "a plan appears twice");
+    if (plan->device != plans[0]->device) return fail(plan, NLINV_E_ARG, "the plans must live on one device");
+    if (plan->timer_kid != NLINV_KT_NONE) return fail(plan, NLINV_E_STATE, "a kernel timer is armed");
+    NLV_CHECK(check_ptr(plan, d_z[i], "d_z"));
+    NLV_CHECK(check_ptr(plan, d_xhat[i], "d_xhat"));
+    NLV_CHECK(check_ptr(plan, d_xprev[i], "d_xprev", true));
+    NLV_CHECK(check_ptr(plan, d_img[i], "d_img", true));
+    if (init[i] < 0 || init[i] > 2) return fail(plan, NLINV_E_ARG, "init must be 0, 1 or 2");
+    if (init[i] == 2 && !d_xprev[i]) return fail(plan, NLINV_E_ARG, "init = 2 needs d_xprev");
+    if (d_xprev[i] && (const void*)d_xprev[i] == (const void*)d_xhat[i])
+      return fail(plan, NLINV_E_ARG, "d_xhat must not alias d_xprev");
+    NLV_CHECK(turns_of(plan, h_turn[i], &turns[i]));
+    ids.push_back(plan->id);
+    key.insert(key.end(), {plan->id, plan->gen, (uint64_t)plan->s.B, (uint64_t)(uintptr_t)d_z[i],
+                           (uint64_t)(uintptr_t)d_xprev[i], (uint64_t)(uintptr_t)d_xhat[i], (uint64_t)init[i],
+                           (uint64_t)(uintptr_t)d_img[i]});
+    for (int b = 0; b < plan->s.B; ++b) key.push_back((uint64_t)(uint32_t)turns[i].t[b]);
+  }
+  nlinv_plan lead = plans[0];
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    auto it = g_multi.find(key);
+    if (it != g_multi.end()) exec = it->second.exec;
+  }
+  if (!exec) {
+    // capture: fork from the lead plan's capture stream into one stream per
+    // plan, each plan's launch sequence on its own, join back
+    for (int i = 0; i < count; ++i)
+      if (!plans[i]->cap_stream)
+        NLV_HIP(plans[i], hipStreamCreateWithFlags(&plans[i]->cap_stream, hipStreamNonBlocking));
+    std::vector<hipEvent_t> ev(count + 1, nullptr);
+    for (auto& e : ev) {
+      const hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (he != hipSuccess) {
+        for (auto& x : ev)
+          if (x) (void)hipEventDestroy(x);
+        return fail_hip(lead, he, "hipEventCreateWithFlags");
+      }
+    }
+    struct Cleanup {
+      std::vector<hipEvent_t>& ev;
+      ~Cleanup() {
+        for (auto& x : ev) (void)hipEventDestroy(x);
+      }
+    } cleanup{ev};
+    hipStream_t origin = lead->cap_stream;
+    hipError_t e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(lead, e, "hipStreamBeginCapture");
+    int rc = NLINV_OK;
+    e = hipEventRecord(ev[0], origin);
+    for (int i = 0; i < count && rc == NLINV_OK && e == hipSuccess; ++i) {
+      nlinv_plan plan = plans[i];
+      hipStream_t br = plan->cap_stream;
+      if (br != origin) e = hipStreamWaitEvent(br, ev[0], 0);
+      if (e != hipSuccess) break;
+      hipStream_t user = plan->stream;
+      plan->stream = br;
+      rc = enqueue_reconstruct(plan, turns[i], reinterpret_cast<const float2*>(d_z[i]),
+                               reinterpret_cast<const float2*>(d_xprev[i]), reinterpret_cast<float2*>(d_xhat[i]),
+                               init[i], 0, plan->p.newton, d_img[i], nullptr);
+      plan->stream = user;
+      if (rc == NLINV_OK && br != origin) {
+        e = hipEventRecord(ev[i + 1], br);
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin, ev[i + 1], 0);
+      }
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(origin, &graph);
+    if (rc != NLINV_OK || e != hipSuccess || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != NLINV_OK) return rc;
+      return fail_hip(lead, e != hipSuccess ? e : ee, "multi-plan capture");
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(lead, e, "hipGraphInstantiate");
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    if (g_multi.size() >= 64) {
+      for (auto& kv : g_multi) (void)hipGraphExecDestroy(kv.second.exec);
+      g_multi.clear();
+    }
+    g_multi.emplace(key, MultiGraph{exec, ids});
+  }
+  NLV_HIP(lead, hipGraphLaunch(exec, lead->stream));
+  for (int i = 0; i < count; ++i) {
+    nlinv_plan plan = plans[i];
+    hipStream_t user = plan->stream;
+    plan->stream = lead->stream;
+    const int rc = check_finite(plan, reinterpret_cast<float2*>(d_xhat[i]), (long long)plan->s.B * plan->s.X);
+    plan->stream = user;
+    NLV_CHECK(rc);
+  }
+  return NLINV_OK;
+}
+
 int nlinv_newton_step(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* d_z, const nlinv_c64* d_xprev,
                       double alpha, int32_t cg, nlinv_c64* d_xhat) {
   NLV_CHECK(check_plan(plan));
@@ -851,9 +987,11 @@ int nlinv_set_coil_weights(nlinv_plan plan, const float* d_winv) {
   NLV_CHECK(check_ptr(plan, d_winv, "d_winv", true));
   float* t = d_winv ? const_cast<float*>(d_winv) : plan->dinv_own;
   if (t != plan->w.dinv) {
-    // captured graphs hold the table's address: drop them
+    // captured graphs hold the table's address: drop them (the multi-plan
+    // graphs are keyed by the generation)
     for (auto& kv : plan->graph_cache) (void)hipGraphExecDestroy(kv.second);
     plan->graph_cache.clear();
+    ++plan->gen;
     plan->w.dinv = t;
   }
   return NLINV_OK;

@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
         "nlinv_nudft": [_P, _P, _P, _P],
         "nlinv_newton_step": [_P, _P, _P, _P, ctypes.c_double, _I, _P],
         "nlinv_apply_normal_multi": [_I, _P, _P, _P, _P, _P, _P],
+        "nlinv_reconstruct_multi": [_I, _P, _P, _P, _P, _P, _P, _P],
         "nlinv_set_coil_weights": [_P, _P],
         "nlinv_compress": [_P, _P, _I, _P, _P],
         "nlinv_compression_matrix": [_P, _P, _I, _P],
@@ -511,6 +512,52 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def reconstruct_multi(plans, zs, turns, xprevs=None, xhats=None, inits=None, imgs=None,
+                      want_img: bool = False):
+    """One frame on each plan as one launch (nlinv_reconstruct_multi): a HIP
+    graph with one independent branch per plan, launched on the first plan's
+    stream.  Per plan i: zs[i] [B][J][R][R], turns[i] (B turns), xprevs[i]
+    [B][X] or None, xhats[i] [B][X] (allocated if None), inits[i] as in
+    Plan.reconstruct, imgs[i] [B][R][R] float32 or None.  Returns (xhats, imgs)."""
+    import torch
+    n = len(plans)
+    xprevs = [None] * n if xprevs is None else list(xprevs)
+    xhats = [None] * n if xhats is None else list(xhats)
+    inits = [None] * n if inits is None else list(inits)
+    imgs = [None] * n if imgs is None else list(imgs)
+    if not (len(zs) == len(turns) == len(xprevs) == len(xhats) == len(inits) == len(imgs) == n):
+        raise ValueError("one set of arguments per plan")
+    for i, pl in enumerate(plans):
+        pl._t(zs[i], torch.complex64, (pl.B, pl.J, pl.R, pl.R), "z")
+        pl._t(xprevs[i], torch.complex64, (pl.B, pl.X), "xprev", allow_none=True)
+        if xhats[i] is None:
+            xhats[i] = pl.empty(pl.B, pl.X)
+            if inits[i] is None:
+                inits[i] = 2 if xprevs[i] is not None else 1
+        elif inits[i] is None:
+            inits[i] = 0
+        pl._t(xhats[i], torch.complex64, (pl.B, pl.X), "xhat")
+        if want_img and imgs[i] is None:
+            imgs[i] = pl.empty(pl.B, pl.R, pl.R, dtype=torch.float32)
+        pl._t(imgs[i], torch.float32, (pl.B, pl.R, pl.R), "img", allow_none=True)
+    plans[0]._stream_sync()
+    P = ctypes.c_void_p
+    handles = (P * n)(*[pl.handle for pl in plans])
+    tl = [plans[i]._turns(turns[i]) for i in range(n)]
+    tp = (P * n)(*[ctypes.cast(t, P) for t in tl])
+    zp = (P * n)(*[z.data_ptr() for z in zs])
+    pp = (P * n)(*[(x.data_ptr() if x is not None else None) for x in xprevs])
+    xp = (P * n)(*[x.data_ptr() for x in xhats])
+    ip = (ctypes.c_int32 * n)(*[int(v) for v in inits])
+    gp = (P * n)(*[(g.data_ptr() if g is not None else None) for g in imgs])
+    rc = load().nlinv_reconstruct_multi(n, handles, zp, tp, pp, xp, ip, gp)
+    if rc != OK:
+        msgs = [load().nlinv_last_error(h) for h in [pl.handle for pl in plans] + [None]]
+        msg = next((m.decode() for m in msgs if m), "")
+        raise NlinvError(rc, msg)
+    return xhats, imgs
 
 
 def apply_normal_multi(plans, turns, xhats, alphas, ps, qs=None):

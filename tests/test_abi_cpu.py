@@ -111,6 +111,12 @@ def test_null_plan_rejected(lib):
     arr = (ctypes.c_void_p * 1)(None)
     alpha = (ctypes.c_double * 1)(0.0)
     assert lib.nlinv_apply_normal_multi(1, one, arr, arr, alpha, arr, arr) == nl.E_ARG
+    # the one-launch multi-plan reconstruction
+    inits = (ctypes.c_int32 * 1)(1)
+    assert lib.nlinv_reconstruct_multi(0, None, None, None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_reconstruct_multi(9, None, None, None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_reconstruct_multi(1, None, None, None, None, None, None, None) == nl.E_ARG
+    assert lib.nlinv_reconstruct_multi(1, one, arr, arr, arr, arr, inits, arr) == nl.E_ARG
 
 
 def test_static_plan_rejects_oversized_parameters(lib):
