@@ -888,8 +888,10 @@ int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_
   }
   nlinv_plan lead = plans[0];
   hipGraphExec_t exec = nullptr;
+  // the table is process-wide: held from the lookup through the launch, so no
+  // other thread's eviction can release the graph in between
+  std::unique_lock<std::mutex> lk(g_multi_mu);
   {
-    std::lock_guard<std::mutex> lk(g_multi_mu);
     auto it = g_multi.find(key);
     if (it != g_multi.end()) exec = it->second.exec;
   }
@@ -945,7 +947,6 @@ int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail_hip(lead, e, "hipGraphInstantiate");
-    std::lock_guard<std::mutex> lk(g_multi_mu);
     if (g_multi.size() >= 64) {
       for (auto& kv : g_multi) (void)hipGraphExecDestroy(kv.second.exec);
       g_multi.clear();
@@ -953,6 +954,7 @@ int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_
     g_multi.emplace(key, MultiGraph{exec, ids});
   }
   NLV_HIP(lead, hipGraphLaunch(exec, lead->stream));
+  lk.unlock();
   for (int i = 0; i < count; ++i) {
     nlinv_plan plan = plans[i];
     hipStream_t user = plan->stream;
