@@ -252,7 +252,10 @@ int nlinv_reconstruct(nlinv_plan plan, const nlinv_c64* d_z, const int32_t* h_tu
  *   d_xhat  [count][X]        out: results
  *   d_img, d_coils            as nlinv_reconstruct ([count] items), or NULL
  * Newton steps m < M-1 of every frame start from, and are regularised
- * towards, d_xprev; they run as one batch.  Step M-1 of frame n0+k is
+ * towards, d_xprev; they run as one batch (groups of 2 or 3 frames in the
+ * four-pass CG form, not on the static workspace: as one chain per frame on
+ * streams the plan creates on first use, forked from and joined back into its
+ * stream, with the same results).  Step M-1 of frame n0+k is
  * regularised towards frame n0+k-1 (d_xprev for k = 0) and runs after it, one
  * frame at a time; with M = 1 that step also starts from frame n0+k-1.
  * count = 1 gives the strict per-frame order (nlinv_reconstruct with init =
@@ -308,7 +311,8 @@ int nlinv_apply_normal(nlinv_plan plan, const int32_t* h_turn, const nlinv_c64* 
  * graphs are kept per argument set (at most 64 sets in the process, then all
  * are dropped), and those of a plan are dropped when it is destroyed or its
  * coil weights change.  NLINV_E_STATE while a kernel timer is armed on one of
- * the plans; NLINV_E_ARG for a plan given twice or plans on different devices. */
+ * the plans or for a plan on the static workspace (those launch eagerly);
+ * NLINV_E_ARG for a plan given twice or plans on different devices. */
 #define NLINV_MAX_MULTI 8
 int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_c64* const* d_z,
                             const int32_t* const* h_turn, const nlinv_c64* const* d_xprev,

@@ -875,6 +875,7 @@ int nlinv_reconstruct_multi(int32_t count, const nlinv_plan* plans, const nlinv_
       if (plans[k] == plan) return fail(plan, NLINV_E_ARG, "a plan appears twice");
     if (plan->device != plans[0]->device) return fail(plan, NLINV_E_ARG, "the plans must live on one device");
     if (plan->timer_kid != NLINV_KT_NONE) return fail(plan, NLINV_E_STATE, "a kernel timer is armed");
+    if (plan->is_static) return fail(plan, NLINV_E_STATE, "plans on the static workspace launch eagerly");
     NLV_CHECK(check_ptr(plan, d_z[i], "d_z"));
     NLV_CHECK(check_ptr(plan, d_xhat[i], "d_xhat"));
     NLV_CHECK(check_ptr(plan, d_xprev[i], "d_xprev", true));
@@ -1040,7 +1041,8 @@ static Bufs item_view(const Bufs& w, const Shape& s, int k) {
 // 10.7 ms, six-pass form 9.8 against 7.8, so only small groups of the
 // four-pass form take this path).
 static bool members_side_by_side(nlinv_plan plan, int count) {
-  return cg_passes(plan) == 4 && count >= 2 && count <= 3 && plan->timer_kid == NLINV_KT_NONE;
+  // not for plans on the static workspace, whose calls create no streams
+  return cg_passes(plan) == 4 && count >= 2 && count <= 3 && plan->timer_kid == NLINV_KT_NONE && !plan->is_static;
 }
 
 static int enqueue_members(nlinv_plan plan, int count, const nlv::TurnArgs& turns, const float2* z,
