@@ -94,3 +94,9 @@ def test_multi_reconstruction_rejects_bad_sets(torch):
         nl.reconstruct_multi([plan], [z], [turns])
     assert e.value.code == nl.E_STATE
     plan.close()
+    st = nl.Plan(32, 4, 5, newton=M, cg=C, static_workspace=True)   # static plans launch eagerly
+    zs = torch.zeros(1, 4, 32, 32, dtype=torch.complex64, device="cuda")
+    with pytest.raises(nl.NlinvError) as e:
+        nl.reconstruct_multi([st], [zs], [[0]])
+    assert e.value.code == nl.E_STATE
+    st.close()
