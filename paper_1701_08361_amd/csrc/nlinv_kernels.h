@@ -534,7 +534,7 @@ k_toep_rows_ragged(ToepShape s0, ToepShape s1, ToepShape s2) {
 // EARLY (the four-pass CG form, whose batch-1 chain is latency-bound): the
 // coil image and rho values are loaded together with the column, so that the
 // pass has one memory round trip before its first transform and none after it
-// (at the cost of registers: 2 waves per SIMD instead of 3)
+// (at G = 320 still within 3 waves per SIMD: 152 VGPRs)
 template <int G, int TWC, int MODE, class S2, bool EARLY = false>
 __global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const float2* __restrict__ xh,
