@@ -55,12 +55,15 @@ def test_multi_reconstruction_equals_per_plan(torch):
 
     def check(xprevs, inits, what):
         ref = _per_plan(plans, zs, turns, xprevs, inits)
-        for rep in range(2):   # capture, then a replay of the cached graph
+        for rep in range(3):   # capture, then replays of the cached graph
             xs, imgs = nl.reconstruct_multi(plans, zs, turns, xprevs=xprevs, inits=inits, want_img=True)
             torch.cuda.synchronize()
             for i in range(n):
                 assert torch.equal(xs[i], ref[i][0]) and torch.equal(imgs[i], ref[i][1]), (what, rep, i)
-        print(f"{what}: every plan equals its own reconstruction (capture and replay)")
+            # eager work on the same workspaces between the replays
+            plans[rep % n].reconstruct(zs[rep % n], turns[rep % n], init=1)
+            torch.cuda.synchronize()
+        print(f"{what}: every plan equals its own reconstruction (capture and two replays)")
         return ref
 
     ref = check([None] * n, [1] * n, "unit start")
