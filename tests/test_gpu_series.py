@@ -284,3 +284,41 @@ def test_uneven_resolutions_share_a_batch(torch):
         assert torch.equal(i2[0], ia[0]) and torch.equal(pa.crop(i2[0]), pa.crop(ia[0])), f
         assert torch.equal(x2[1], xb[0]) and torch.equal(i2[1], ib[0]), f
     print("uneven resolutions: bit for bit")
+
+
+def test_relaxed_group_side_by_side_graphs_match_eager(torch):
+    """A relaxed group of three frames in the four-pass form (its shared Newton
+    steps as one chain per member on streams of their own, forked from and
+    joined back into the plan's stream) gives the same bits eagerly and as a
+    captured graph, over replays with eager runs of the group in between, and
+    matches the oracle's relaxed schedule."""
+    N, J, K, U, M, C = 32, 4, 7, 3, 3, 5
+    print_case("relaxed group side by side, graphs", N=N, J=J, K=K, U=U, M=M, C=C)
+    ser = synth.real_time_series(seed=23, N=N, J=J, J_phys=6, K=K, U=U, frames=4)
+    plan = nl().Plan(N, J, K, U=U, batch=3, newton=M, cg=C, cg_passes=4)
+    z = _grid_all(torch, plan, ser, range(4))
+    plan.set_batch(1)
+    x0, _, _ = plan.reconstruct(z[0:1], [int(ser.turn[0])], init=1)
+    plan.set_batch(3)
+    turns = [int(t) for t in ser.turn[1:4]]
+    ref, refi, _ = plan.reconstruct_frames(z[1:4], turns, xprev=x0[0], want_img=True)
+    torch.cuda.synchronize()
+    ref, refi = ref.clone(), refi.clone()
+    for rep in range(3):
+        plan.set_graphs(True)
+        f, i, _ = plan.reconstruct_frames(z[1:4], turns, xprev=x0[0], want_img=True)
+        torch.cuda.synchronize()
+        assert torch.equal(f, ref) and torch.equal(i, refi), rep
+        plan.set_graphs(False)
+        f, _, _ = plan.reconstruct_frames(z[1:4], turns, xprev=x0[0])
+        torch.cuda.synchronize()
+        assert torch.equal(f, ref), rep
+    # the oracle's relaxed schedule: frame 0 strict, frames 1..3 one group
+    g = O.Geometry.make(N, J)
+    Ps = [O.psf_kernel(ser.traj[f], g.R, g.G) for f in range(4)]
+    zs = [O.grid(ser.y[f], ser.traj[f], g.R) for f in range(4)]
+    xo = O.reconstruct_series(g, zs, Ps, O.relaxed_sources(4, 0, 3), newton=M, cg_iters=C)
+    imgs = host(refi)
+    worst = max(rel(imgs[k], O.image(g, xo[k + 1])) for k in range(3))
+    print(f"relaxed group side by side: graphs equal eager; worst image rel vs oracle {worst:.2e}")
+    assert worst < IMG_TOL
