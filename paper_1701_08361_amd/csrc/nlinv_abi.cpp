@@ -162,10 +162,8 @@ int derive(const nlinv_params* p, Shape* s, Layout* L, std::string* err) {
   if (!tab) return bad(NLINV_E_SIZE, "no kernels for this grid size");
   S.NX3 = (S.J * S.GC + tab->row_lines - 1) / tab->row_lines;
   S.NRQ = (S.R * S.R + 64 * nlv::RHOQ_E - 1) / (64 * nlv::RHOQ_E);
-  S.NCI = (S.R * S.R + nlv::CHUNK - 1) / nlv::CHUNK;
   S.NCH = (int)((S.X + nlv::CHUNK - 1) / nlv::CHUNK);
   int st = S.NX3 + S.NRQ;
-  if (S.NX3 + S.NCI > st) st = S.NX3 + S.NCI;
   if (S.NCH > st) st = S.NCH;
   S.stride = st;
   S.coltile = p->col_tile;
@@ -702,9 +700,8 @@ static int enqueue_newton_step(nlinv_plan plan, const nlv::TurnArgs& turns, cons
   NLV_HIP(plan, timed(plan, NLINV_KT_COILH_ROWS, [&] {
             return plan->t->coilh_rows(sg, w, st, 1, nullptr, xh, xp, alpha, w.Rv, w.Pv[0]);
           }));
-  NLV_HIP(plan, nlv::launch_cg_init(s, w, st, xh, xp, alpha));
-
-  int ncur = s.NX3 + s.NCI, nprev = 0;
+  // (the image block of b rides in the coil-adjoint pass's image blocks)
+  int ncur = s.NX3 + s.NRQ, nprev = 0;
   if (cg_passes(plan) == 4) {
     // four dependent kernels per CG iteration (see the four-pass section of
     // nlinv_kernels.h): the direction update, the x-stage of W^-1 p and the

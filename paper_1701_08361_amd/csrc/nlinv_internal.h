@@ -76,7 +76,6 @@ struct Shape {
   int NT;              // column tiles per channel (R / TW)
   int NX3;             // coil row blocks per item (ceil(J * GC / row_lines))
   int NRQ;             // q_rho blocks per item of the coil-adjoint rows (ceil(R*R / (64 * RHOQ_E)))
-  int NCI;             // rho-block chunks (ceil(R*R / CHUNK))
   int NCH;             // vector chunks (ceil(X / CHUNK))
   int stride;          // partial slots per item
   int gsplit;          // sample-range split of the gridding kernel (1 = none)
@@ -210,8 +209,6 @@ struct GTable {
 const GTable* table_for(int G);
 
 // Grid-size independent launchers.
-hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
-                          const float2* xprev, double alpha);
 hipError_t launch_cg_update(const Shape& s, const Bufs& w, hipStream_t st, int iter, int last,
                             const double2* p, Partials rr, float2* xh);
 // out (float32 [B][X]) = (sum_j PR_j + alpha p ; Q) ; p may be null; without the image

@@ -635,7 +635,9 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
 // MODE 0: q = W^-H(.) + alpha p  (partials Re<p, q> -> part at slot_off + block);
 //         nr further blocks per item form the image block of q,
 //         q_rho = sum_j PR_j + alpha p_rho (channel sum in channel order, FP64)
-// MODE 1: b = W^-H(.) - alpha (x - x_prev) -> out, out2 (partials |b|^2)
+// MODE 1: b = W^-H(.) - alpha (x - x_prev) -> out, out2 (partials |b|^2);
+//         nr further blocks per item form the image block of b,
+//         b_rho = sum_j PR_j - alpha (rho - rho_prev)
 // MODE 2: raw W^-H(.) -> out
 // ---------------------------------------------------------------------------
 template <int G, int MODE>
@@ -675,6 +677,47 @@ k_coilh_rows(const double2* __restrict__ U4, const float* __restrict__ dinv, con
           out[ve] = make_double2(qx, qy);
           acc += p.x * qx + p.y * qy;
         }
+      }
+      const double s = block_sum_waves<NTH>(acc, sh);
+      if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + chunk] = s;
+      return;
+    }
+  }
+  if constexpr (MODE == 1) {
+    if (chunk >= nb) {   // block-uniform: image block of the right-hand side,
+      // b_rho = sum_j PR_j - alpha (rho - rho_prev) (channel sum in channel
+      // order), one pixel per lane, into out and out2, |b|^2 partials beside
+      // those of the coil block; the channel products are loaded up front
+      // (indices clamped to J - 1, only k < J summed), the rest after them
+      const int e = (chunk - nb) * NTH + (int)threadIdx.x;
+      double acc = 0.0;
+      if (e < R * R) {
+        constexpr int JP = 16;
+        float2 prv[JP];
+        sfor<0, JP>([&](auto c) {
+          constexpr int k = decltype(c)::value;
+          prv[k] = PR[((size_t)b * J + (k < J ? k : J - 1)) * R * R + e];
+        });
+        const size_t ve = (size_t)b * X + e;
+        const float2 rho = xh[ve];
+        const float2 rp = xprev ? xprev[ve] : make_float2(1.f, 0.f);
+        double sx = 0.0, sy = 0.0;
+        sfor<0, JP>([&](auto c) {
+          constexpr int k = decltype(c)::value;
+          if (k < J) {
+            sx += prv[k].x;
+            sy += prv[k].y;
+          }
+        });
+        for (int jj = JP; jj < J; ++jj) {
+          const float2 pr = PR[((size_t)b * J + jj) * R * R + e];
+          sx += pr.x;
+          sy += pr.y;
+        }
+        const double2 bv = make_double2(sx - alpha * ((double)rho.x - rp.x), sy - alpha * ((double)rho.y - rp.y));
+        out[ve] = bv;
+        out2[ve] = bv;
+        acc = bv.x * bv.x + bv.y * bv.y;
       }
       const double s = block_sum_waves<NTH>(acc, sh);
       if (threadIdx.x == 0) part[(size_t)b * stride + slot_off + chunk] = s;
@@ -1401,7 +1444,8 @@ struct GLaunch {
   static hipError_t coilh_rows(const Shape& s, const Bufs& w, hipStream_t st, int mode, const double2* pv,
                                const float2* xh, const float2* xprev, double alpha, double2* out,
                                double2* out2) {
-    const int nr = mode == 0 ? s.NRQ : 0;
+    // modes 0 and 1: NRQ image blocks per item after the line blocks
+    const int nr = mode <= 1 ? s.NRQ : 0;
     const int blocks = s.B * (s.NX3 + nr);
     double* part = mode == 1 ? w.rr[0] : w.pq;
     const int off = 0;

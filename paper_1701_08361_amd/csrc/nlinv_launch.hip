@@ -37,35 +37,6 @@ __device__ __forceinline__ double2 ldv(const float2* __restrict__ p, size_t i) {
 }
 __device__ __forceinline__ float2 tof(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
-// Image block of the Newton right-hand side: b_rho = sum_j PR_j - alpha (rho - rho_prev);
-// r = p = b_rho; partials |b_rho|^2 -> rr0[b][slot_off + chunk].
-__global__ void __launch_bounds__(VT)
-k_cg_init(const float2* __restrict__ PR, const float2* __restrict__ xh, const float2* __restrict__ xprev,
-          double alpha, double2* __restrict__ Rv, double2* __restrict__ P0, double* __restrict__ rr0,
-          int stride, int slot_off, int J, int RR, long long X, int nchunk) {
-  __shared__ double sh[VT];
-  const int b = blockIdx.x / nchunk, c = blockIdx.x - b * nchunk;
-  const int e0 = c * CHUNK, e1 = min(RR, e0 + CHUNK);
-  double acc = 0.0;
-  for (int e = e0 + threadIdx.x; e < e1; e += VT) {
-    double sx = 0.0, sy = 0.0;
-    for (int j = 0; j < J; ++j) {
-      const float2 pr = PR[((size_t)b * J + j) * RR + e];
-      sx += pr.x;
-      sy += pr.y;
-    }
-    const size_t ve = (size_t)b * X + e;
-    const float2 rho = xh[ve];
-    const float2 rp = xprev ? xprev[ve] : make_float2(1.f, 0.f);
-    const double2 bv = make_double2(sx - alpha * ((double)rho.x - rp.x), sy - alpha * ((double)rho.y - rp.y));
-    Rv[ve] = bv;
-    P0[ve] = bv;
-    acc += bv.x * bv.x + bv.y * bv.y;
-  }
-  const double s = block_sum_waves<VT>(acc, sh);
-  if (threadIdx.x == 0) rr0[(size_t)b * stride + slot_off + c] = s;
-}
-
 // CG step: a = rr / Re<p, q>; h += a p; r -= a q; rr' partials.  q is complete in Q
 // (its image block formed by the q_rho blocks of the coil-adjoint rows).
 // On the last iteration the Newton update x += h is applied instead of the r update.
@@ -434,13 +405,6 @@ __global__ void k_fill_int(int* __restrict__ p, int v) {
 
 hipError_t launch_fill_int(hipStream_t st, int* p, int v) {
   k_fill_int<<<1, 64, 0, st>>>(p, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_init(const Shape& s, const Bufs& w, hipStream_t st, const float2* xh,
-                          const float2* xprev, double alpha) {
-  k_cg_init<<<s.B * s.NCI, VT, 0, st>>>(w.PR, xh, xprev, alpha, w.Rv, w.Pv[0], w.rr[0], s.stride,
-                                        s.NX3, s.J, s.R * s.R, s.X, s.NCI);
   return hipGetLastError();
 }
 
