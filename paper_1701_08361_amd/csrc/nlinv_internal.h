@@ -92,8 +92,9 @@ struct Shape {
 // the blocks of launches too small to fill the GPU; measured at 160 px they
 // speed up the forward pass of a batch-1 launch alone, yet the whole solve
 // runs slower (plain series 164.8 against 166.9 frames/s with four columns in
-// the forward pass of small launches only), so four is a schedule to measure,
-// not a default.
+// the forward pass of small launches only; with the four-pass CG iteration
+// 190.3 against 198.3, and 176.7 with four columns in both passes), so four
+// is a schedule to measure, not a default.
 inline int col_tile(const Shape& s, bool /*forward*/) { return s.coltile == 4 ? 4 : TW; }
 
 // Gridding work decomposition (channels per block; sample-range split).
