@@ -311,6 +311,21 @@ k_coil_rows(const V* __restrict__ src, const double2* __restrict__ rsrc, double2
 // MODE 1: u = c_j d_rho + rho d_c_j -> out (U2);  MODE 2 / 3: as 0 / 1 but u -> out (image, float32)
 // pv: the direction (MODE 1 / 3), its rho block already updated by coil_rows.
 // ---------------------------------------------------------------------------
+// Block order of the column passes.  The blocks of a launch are dealt to the
+// eight XCDs in turn (block i to XCD i mod 8), each with its own L2.  Block i
+// takes the work item col_order(i, n) (n blocks), with the channel fastest:
+// each XCD works through a contiguous run of work items, so the J channel
+// blocks of one column tile run on one XCD at about the same time and share
+// its cached rho and direction columns.
+__device__ __forceinline__ void col_order(int i, int n, int J, int NT, int& bj, int& tile) {
+  constexpr int NX = 8;
+  const int k = i % NX, q = n / NX, r = n % NX;
+  const int w = k * q + (k < r ? k : r) + i / NX;
+  const int j = w % J, bt = w / J;
+  tile = bt % NT;
+  bj = (bt / NT) * J + j;
+}
+
 template <int G, int TWC, int MODE, class S2>
 __global__ void __launch_bounds__((cols_threads<G, TWC>()))
 k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2* __restrict__ xh,
@@ -323,7 +338,9 @@ k_cols_fwd(const double2* __restrict__ U1, float2* __restrict__ co, const float2
   __shared__ C lds[TWC * T::LDSC];
   const bool act = (int)threadIdx.x < TWC * T::SIZE;
   const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
-  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
+  int tile, bj;
+  col_order((int)blockIdx.x, (int)gridDim.x, J, NT, bj, tile);
+  const int b = bj / J;
   const int x = tile * TWC + col;
   C* L = lds + col * T::LDSC;
 
@@ -559,7 +576,14 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   }
   const bool act = (int)threadIdx.x < TWC * T::SIZE;
   const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
-  const int tile = blockIdx.x % NT, bj = blockIdx.x / NT, b = bj / J;
+  // the four-pass form (batch 1: every block resident at once) keeps the
+  // plain order
+  int tile = (int)blockIdx.x % NT, bj = (int)blockIdx.x / NT;
+  if constexpr (!EARLY) {
+    const int n = (MODE == 0 && red.scal) ? red.nbase : (int)gridDim.x;
+    col_order((int)blockIdx.x, n, J, NT, bj, tile);
+  }
+  const int b = bj / J;
   const int x = tile * TWC + col;
   C* L = lds + col * T::LDSC;
   const size_t img = (size_t)bj * R * R;
