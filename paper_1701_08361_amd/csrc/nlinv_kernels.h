@@ -577,7 +577,8 @@ k_cols_back(const void* __restrict__ inp, const float2* __restrict__ co, const f
   const bool act = (int)threadIdx.x < TWC * T::SIZE;
   const int col = act ? (int)threadIdx.x % TWC : 0, tl = act ? (int)threadIdx.x / TWC : T::SIZE;
   // the four-pass form (batch 1: every block resident at once) keeps the
-  // plain order
+  // plain order (channel-fastest there, with its forward pass: plain series
+  // 197.5 against 198.3 frames/s)
   int tile = (int)blockIdx.x % NT, bj = (int)blockIdx.x / NT;
   if constexpr (!EARLY) {
     const int n = (MODE == 0 && red.scal) ? red.nbase : (int)gridDim.x;
