@@ -454,6 +454,27 @@ def test_batched_items_equal_plain_c2(torch, c2_oracle, cg_passes):
         assert torch.equal(xb[b], x1[0]) and torch.equal(ib[b], i1[0]), b
 
 
+def test_batched_items_equal_plain_past_the_infinity_cache(torch, c2_oracle):
+    """A batch whose half-transformed grid (36 x 10 x 320 x 160 x 16 B = 295 MB)
+    exceeds the 256 MiB Infinity Cache runs its column passes in the other
+    block order (tile fastest instead of channel fastest); its items still
+    reconstruct the batch-1 plan's bits."""
+    B = 36
+    print_case("batched c2 items past the cache", N=160, J=10, K=15, M=7, C=20, B=B, cg_passes=6)
+    assert B * 10 * 320 * 160 * 16 > 256 << 20
+    ser, g, refs = c2_oracle
+    one = nl().Plan(160, 10, 15, U=5, newton=7, cg=20, cg_passes=6)
+    t = int(ser.turn[0])
+    z = one.grid(dev(torch, ser.traj[0:1]), dev(torch, ser.y[0:1]), turns=[t])
+    x1, i1, _ = one.reconstruct(z, [t], want_img=True)
+    many = nl().Plan(160, 10, 15, U=5, batch=B, newton=7, cg=20, cg_passes=6)
+    many.psf(dev(torch, ser.traj[0]), t)
+    zb = z.expand(B, -1, -1, -1).contiguous()
+    xb, ib, _ = many.reconstruct(zb, [t] * B, want_img=True)
+    for b in (0, 17, B - 1):
+        assert torch.equal(xb[b], x1[0]) and torch.equal(ib[b], i1[0]), b
+
+
 def test_check_finite_flag(torch):
     """NLINV_F_CHECK_FINITE: a clean reconstruction syncs fine; a non-finite
     input sample makes the next nlinv_sync report NLINV_E_NONFINITE once (the
