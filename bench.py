@@ -793,6 +793,27 @@ def roofline(kt_by_batch, head_batch):
             "storage_gbs": head["storage_gbs"], "by_batch": by}
 
 
+def copy_gbs(torch, mib=1024, reps=10):
+    """Rate of a plain device-to-device copy of `mib` MiB (the runtime's copy
+    kernel), bytes read plus bytes written per second: what the HBM delivers
+    to a kernel that only streams, beside the published 8 TB/s.  1 GiB is four
+    times the 256 MB Infinity Cache."""
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * n / t / 1e9
+
+
 def cpu_baseline():
     """The FP64 oracle as it stands, on the host cores, on bounded samples:
       all threads : frame 0 of the 160 px series (exact gridding, PSF kernel,
@@ -1108,7 +1129,12 @@ def main():
                      "hip_graphs": args.graphs,
                      "data_gen_s": round(t_gen, 1)}
     if kt_by_batch:
-        out["roofline"] = roofline(kt_by_batch, args.batch if batch_data is not None else 1)
+        rl = roofline(kt_by_batch, args.batch if batch_data is not None else 1)
+        if rl is not None:
+            cg = copy_gbs(torch)
+            rl["attainable"] = {"copy_gbs": cg, "storage_frac_of_copy": rl["storage_gbs"] / cg,
+                                "form": "1 GiB device-to-device copy (read + written bytes per second)"}
+        out["roofline"] = rl
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
